@@ -1,0 +1,214 @@
+/*
+ * figaro.h -- C ABI of the MI355X library that computes the upper-triangular
+ * factor R of the QR decomposition of the data columns of an acyclic natural
+ * join, without materialising the join.
+ *
+ * The problem statement follows the paper's setup section ("Input" and
+ * "Output"): the input is a database of relations S_1..S_r together with a
+ * join tree; the output is the R of A[:Y], the data columns of the join.  R is
+ * returned upper triangular with a non-negative diagonal, which makes it unique
+ * whenever A has full column rank.
+ *
+ * Model.
+ *  - A relation has `rows` tuples, `num_keys` join attributes (identified by
+ *    global attribute ids; equal ids are compared for equality, which is the
+ *    natural join) and `num_cols` real data columns.
+ *  - Key attributes are join attributes only: every key attribute of a
+ *    relation must be shared with its parent or with one of its children in
+ *    the join tree.  A relation with no key attributes joins its parent by
+ *    Cartesian product.
+ *  - The join tree is given by `parent` (-1 for exactly one root).  For every
+ *    attribute, the relations containing it must form a connected subtree
+ *    (running intersection).
+ *  - Tuples are a bag: duplicate tuples each count.  Dangling tuples (tuples
+ *    that occur in no join row) are removed by the plan (semi-join reduction);
+ *    the paper assumes a fully reduced database, and R is unchanged by the
+ *    removal.
+ *  - Columns of R are ordered by relation index, then by column order within
+ *    a relation; key attributes are not columns of R.
+ *
+ * Layouts.  Key columns are device arrays, column-major [num_keys][rows] of
+ * int32 or int64.  Data values are FP64, column-major: column c of relation i
+ * starts at values[i] + c * ld[i], ld[i] >= rows.  R is FP64 column-major
+ * n x n (leading dimension n), n = sum of num_cols.
+ *
+ * Row order.  The compute calls take the values of every relation in *plan
+ * order*: rows sorted by the relation's key attributes (the paper's
+ * algorithms assume sorted inputs), with only the rows that survive the
+ * reduction.  figaro_plan_permutation() gives the permutation and
+ * figaro_permute_values() applies it on the device.
+ *
+ * Ownership and concurrency.  The caller owns every buffer it passes.  The
+ * plan owns a device workspace, allocated in figaro_plan_create(); the compute
+ * calls allocate nothing and do not synchronise the host, and enqueue all work
+ * on the given stream.  Calls that use the same plan share its workspace and
+ * must be serialised on one stream.
+ *
+ * Errors.  Every call returns a figaro_status; nothing is thrown across the
+ * ABI.  figaro_last_error() returns a message for the last failing call on a
+ * plan (or, for a NULL plan, the last failing call of the calling thread).
+ * NaN or Inf values propagate into R and are not an error.
+ */
+#ifndef FIGARO_H
+#define FIGARO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct figaro_plan_s *figaro_plan_t;
+
+typedef enum {
+    FIGARO_OK = 0,
+    FIGARO_EINVAL = 1,          /* bad argument (NULL pointer, size, dtype, ld) */
+    FIGARO_ENOTTREE = 2,        /* parents do not form one tree, or running intersection fails */
+    FIGARO_EUNSHARED_KEY = 3,   /* a key attribute shared with no neighbour in the tree */
+    FIGARO_EEMPTY_JOIN = 4,     /* the join has no rows */
+    FIGARO_EOVERFLOW = 5,       /* a count query value reaches 2^53 */
+    FIGARO_ESINGULAR = 6,       /* R has a zero diagonal entry (backward pass) */
+    FIGARO_ENOMEM = 7,          /* device allocation failed */
+    FIGARO_EHIP = 8,            /* a HIP runtime call failed */
+    FIGARO_EUNSUPPORTED = 9     /* a size beyond what this build supports */
+} figaro_status;
+
+/* One relation of the database. */
+typedef struct {
+    int64_t rows;               /* number of tuples m_i >= 0 */
+    int32_t num_keys;           /* number of join attributes k_i >= 0 */
+    const int32_t *key_attr;    /* host [k_i]: global attribute ids, distinct */
+    const void *key_cols;       /* device [k_i][rows] int32 or int64 */
+    int32_t key_dtype;          /* 4 (int32) or 8 (int64) */
+    int32_t num_cols;           /* number of FP64 data columns n_i >= 1 */
+    int32_t parent;             /* index of the parent relation, -1 for the root */
+} figaro_relation_desc;
+
+/* Tuning knobs of a plan; pass NULL for defaults. */
+typedef struct {
+    int32_t tile_items;         /* items per tile of the segmented head/tail
+                                   kernels; 0 = default (chosen per column
+                                   count).  Smaller tiles split key groups
+                                   across tiles, which exercises the
+                                   two-level head/tail combination. */
+    int32_t waves_per_task;     /* upper bound on waves of one head/tail
+                                   launch, 0 = default */
+    int32_t keys_on_host;       /* 1: key_cols are host pointers */
+    int32_t analyze_only;       /* 1: stop after the count queries; the plan
+                                   then answers the info and count queries
+                                   only, holds no device memory, and the
+                                   compute calls return FIGARO_EINVAL */
+} figaro_plan_options;
+
+/* Count-query selectors for figaro_plan_counts(). */
+typedef enum {
+    FIGARO_COUNT_ROWS_PER_KEY = 0,   /* |S_i^{x_i}|, per key group x_i */
+    FIGARO_COUNT_THETA_DOWN = 1,     /* Theta_i^down(x_i), per key group */
+    FIGARO_COUNT_PHI_CIRC = 2,       /* Phi_i^o(x_i), per key group */
+    FIGARO_COUNT_PHI_UP = 3,         /* Phi_i^up(x_p), per parent group */
+    FIGARO_COUNT_PHI_DOWN = 4        /* Phi_i^down(x_p), per parent group */
+} figaro_count_kind;
+
+/*
+ * Build a plan from the keys (section "Scaling Factors as Count Queries",
+ * Algorithm 2, and the sort order both algorithms assume): validate the tree,
+ * reduce dangling tuples, sort each relation on (attributes shared with the
+ * parent, then its other key attributes, then row index), segment it into key
+ * groups, evaluate the count queries exactly in 64-bit integers, derive the
+ * scale factors, and allocate the workspace.  Reads key_cols on `stream`,
+ * synchronises it, and copies small tables to the device.
+ */
+figaro_status figaro_plan_create(figaro_plan_t *out, int32_t r,
+                                 const figaro_relation_desc *rels,
+                                 const figaro_plan_options *opts,
+                                 hipStream_t stream);
+void figaro_plan_destroy(figaro_plan_t plan);
+
+int32_t figaro_plan_num_relations(figaro_plan_t plan);
+int32_t figaro_plan_num_cols(figaro_plan_t plan);                 /* n */
+int64_t figaro_plan_input_rows(figaro_plan_t plan, int32_t rel);  /* m_i as given */
+int64_t figaro_plan_rows(figaro_plan_t plan, int32_t rel);        /* rows kept in plan order */
+int64_t figaro_plan_dropped_rows(figaro_plan_t plan, int32_t rel);/* dangling tuples removed */
+double  figaro_plan_join_rows(figaro_plan_t plan);                /* |A|, exact below 2^53 */
+int64_t figaro_plan_workspace_bytes(figaro_plan_t plan);
+
+/* perm_host[p] (p < input rows) is the caller row placed at plan row p; the
+ * kept rows come first, the dropped rows after them.  Host output. */
+figaro_status figaro_plan_permutation(figaro_plan_t plan, int32_t rel, int64_t *perm_host);
+
+/* Number of key groups (which = 0: groups of x_i) or parent groups (which = 1:
+ * groups of x_p) of relation rel; -1 on error. */
+int64_t figaro_plan_num_groups(figaro_plan_t plan, int32_t rel, int32_t which);
+/* Caller row index of the first plan row of every group (host output). */
+figaro_status figaro_plan_group_first_rows(figaro_plan_t plan, int32_t rel, int32_t which,
+                                           int64_t *rows_host);
+/* Exact count-query values per group (host output). */
+figaro_status figaro_plan_counts(figaro_plan_t plan, int32_t rel, figaro_count_kind kind,
+                                 int64_t *out_host);
+
+/* dst (plan order, leading dim ld_dst) <- src (caller order, leading dim
+ * ld_src) for the kept rows of relation rel; device pointers, enqueued. */
+figaro_status figaro_permute_values(figaro_plan_t plan, int32_t rel, const double *src,
+                                    int64_t ld_src, double *dst, int64_t ld_dst,
+                                    hipStream_t stream);
+/* dst (caller order) <- src (plan order); rows dropped by the reduction get 0.
+ * Used to return gradients in the caller's row order. */
+figaro_status figaro_unpermute_values(figaro_plan_t plan, int32_t rel, const double *src,
+                                      int64_t ld_src, double *dst, int64_t ld_dst,
+                                      hipStream_t stream);
+
+/*
+ * Forward: R of the join (Algorithm 3 followed by the post-processing QR of
+ * the section "Post-processing", then a non-negative diagonal).
+ *   values[i]: device, plan order, column-major with leading dim ld[i] >= rows
+ *   R: device, n x n column-major; the strictly lower part is written as 0.
+ * Enqueued on `stream`; no allocation, no host synchronisation.
+ */
+figaro_status figaro_r(figaro_plan_t plan, const double *const *values, const int64_t *ld,
+                       double *R, hipStream_t stream);
+
+/*
+ * The intermediate matrix R0 of Theorem 6 (heads and tails before the
+ * post-processing QR), materialised for inspection: figaro_r0_rows() rows of
+ * n columns, column-major with leading dimension ld_r0.  block_of_row
+ * (device int32, may be NULL) receives for each row the id of the block that
+ * produced it: 3*i + 0 for tails of relation i (heads_and_tails), 3*i + 1 for
+ * generalized tails of relation i (project_away_join_attributes), 3*i + 2 for
+ * the heads emitted at the root.  Rows that carry no tail are zero.
+ */
+int64_t figaro_r0_rows(figaro_plan_t plan);
+figaro_status figaro_r0(figaro_plan_t plan, const double *const *values, const int64_t *ld,
+                        double *R0, int64_t ld_r0, int32_t *block_of_row, hipStream_t stream);
+
+/*
+ * Per-kernel timing for benchmarks.  While enabled, the compute calls record a
+ * pair of HIP events on the caller's stream around every kernel launch, in a
+ * pool of `capacity` pairs (events are created here, not in the compute
+ * calls; launches beyond the pool are not timed).  figaro_profile_read()
+ * waits for the recorded events, adds their durations to the totals of each
+ * kernel class, and frees the pool slots.  Classes:
+ *   0 heads_and_tails, first level (unit-count tails + QR accumulation)
+ *   1 project_away_join_attributes, first level (weighted tails + QR)
+ *   2 upper levels of both (combination of tiles of one key group)
+ *   3 process_and_join_children
+ *   4 root heads
+ *   5 post-processing TSQR over the stack of partial R factors
+ *   6 backward kernels
+ * For each class the totals hold: elapsed milliseconds, launches, the
+ * algorithmic bytes (values read, for classes 0-2; gathered and written rows
+ * for 3-4; stack rows read for 5) and the QR flops (2 m n^2 per launch).
+ */
+figaro_status figaro_profile_enable(figaro_plan_t plan, int32_t capacity);   /* 0 disables */
+figaro_status figaro_profile_read(figaro_plan_t plan, int32_t kernel_class, double *ms,
+                                  int64_t *launches, double *bytes, double *flops);
+figaro_status figaro_profile_reset(figaro_plan_t plan);
+
+/* Message of the last failing call on `plan` (NULL: on the calling thread). */
+const char *figaro_last_error(figaro_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIGARO_H */

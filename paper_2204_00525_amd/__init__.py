@@ -1,0 +1,365 @@
+"""MI355X (gfx950) library: R of the QR decomposition of an acyclic natural
+join, computed without materialising the join.
+
+Thin ctypes binding over the C ABI in include/figaro.h.  It only marshals
+arguments (device pointers of torch tensors, leading dimensions, the current
+HIP stream); every step of the computation runs in the library's HIP kernels.
+Loading fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfigaro.so")
+
+FIGARO_OK = 0
+STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOTTREE", 3: "EUNSHARED_KEY", 4: "EEMPTY_JOIN",
+                5: "EOVERFLOW", 6: "ESINGULAR", 7: "ENOMEM", 8: "EHIP", 9: "EUNSUPPORTED"}
+COUNT_KINDS = {"rows_per_key": 0, "theta_down": 1, "phi_circ": 2, "phi_up": 3, "phi_down": 4}
+
+
+class FigaroError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"figaro status {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+
+
+class RelationDesc(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_int64), ("num_keys", ctypes.c_int32),
+                ("key_attr", ctypes.POINTER(ctypes.c_int32)), ("key_cols", ctypes.c_void_p),
+                ("key_dtype", ctypes.c_int32), ("num_cols", ctypes.c_int32), ("parent", ctypes.c_int32)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("tile_items", ctypes.c_int32), ("waves_per_task", ctypes.c_int32),
+                ("keys_on_host", ctypes.c_int32), ("analyze_only", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfigaro.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no fallback implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    pi64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "figaro_plan_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(RelationDesc),
+                                     ctypes.POINTER(PlanOptions), vp]),
+        "figaro_plan_destroy": (None, [vp]),
+        "figaro_plan_num_relations": (i32, [vp]),
+        "figaro_plan_num_cols": (i32, [vp]),
+        "figaro_plan_input_rows": (i64, [vp, i32]),
+        "figaro_plan_rows": (i64, [vp, i32]),
+        "figaro_plan_dropped_rows": (i64, [vp, i32]),
+        "figaro_plan_join_rows": (dbl, [vp]),
+        "figaro_plan_workspace_bytes": (i64, [vp]),
+        "figaro_plan_permutation": (i32, [vp, i32, pi64]),
+        "figaro_plan_num_groups": (i64, [vp, i32, i32]),
+        "figaro_plan_group_first_rows": (i32, [vp, i32, i32, pi64]),
+        "figaro_plan_counts": (i32, [vp, i32, i32, pi64]),
+        "figaro_permute_values": (i32, [vp, i32, vp, i64, vp, i64, vp]),
+        "figaro_unpermute_values": (i32, [vp, i32, vp, i64, vp, i64, vp]),
+        "figaro_r": (i32, [vp, pp, pi64, vp, vp]),
+        "figaro_r0_rows": (i64, [vp]),
+        "figaro_r0": (i32, [vp, pp, pi64, vp, i64, vp, vp]),
+        "figaro_last_error": (ctypes.c_char_p, [vp]),
+        "figaro_profile_enable": (i32, [vp, i32]),
+        "figaro_profile_read": (i32, [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
+                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
+        "figaro_profile_reset": (i32, [vp]),
+        "figaro_debug_stack_rows": (i64, [vp]),
+        "figaro_debug_stack": (i32, [vp, pp, pi64, vp, vp]),
+    }
+    optional = {
+        "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    for name, (res, args) in optional.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int, plan_handle=None):
+    if status != FIGARO_OK:
+        msg = lib().figaro_last_error(plan_handle)
+        raise FigaroError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+class Plan:
+    """A plan over one key structure: validated join tree, reduced and sorted
+    relations, exact count queries, scale factors and a device workspace.
+
+    relations: sequence of objects with attributes key_attrs (list[int]),
+    keys (torch tensor on the GPU, int32 or int64, shape (k, m)), ncols (int)
+    and parent (int, -1 for the root)."""
+
+    def __init__(self, relations: Sequence, *, tile_items: int = 0, waves_per_task: int = 0,
+                 stream=None, analyze_only: bool = False):
+        L = lib()
+        if analyze_only:
+            self._init_host(relations, tile_items, waves_per_task)
+            return
+        import torch
+        self._handle = ctypes.c_void_p()
+        r = len(relations)
+        descs = (RelationDesc * r)()
+        self._keep = []
+        for i, rel in enumerate(relations):
+            attrs = np.ascontiguousarray(np.asarray(rel.key_attrs, dtype=np.int32))
+            keys = rel.keys
+            if keys.numel() and not keys.is_cuda:
+                raise ValueError("key columns must be device tensors")
+            keys = keys.contiguous()
+            self._keep += [attrs, keys]
+            descs[i].rows = int(keys.shape[1]) if keys.dim() == 2 else 0
+            descs[i].num_keys = len(rel.key_attrs)
+            descs[i].key_attr = attrs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            descs[i].key_cols = ctypes.c_void_p(keys.data_ptr() if keys.numel() else 0)
+            descs[i].key_dtype = 8 if keys.dtype == torch.int64 else 4
+            descs[i].num_cols = int(rel.ncols)
+            descs[i].parent = int(rel.parent)
+            if hasattr(rel, "rows_override"):
+                descs[i].rows = int(rel.rows_override)
+        opts = PlanOptions(tile_items, waves_per_task, 0, 0)
+        st = L.figaro_plan_create(ctypes.byref(self._handle), r, descs, ctypes.byref(opts),
+                                  _stream_handle(stream))
+        if st != FIGARO_OK:
+            msg = L.figaro_last_error(None)
+            raise FigaroError(st, msg.decode() if msg else "")
+        self._keep = []
+        self.r = r
+        self.n = L.figaro_plan_num_cols(self._handle)
+        self.ncols = [int(rel.ncols) for rel in relations]
+
+    def _init_host(self, relations, tile_items, waves_per_task):
+        """Keys given as host arrays; only the key analysis runs (validation,
+        reduction, order, count queries).  Needs no GPU."""
+        L = lib()
+        self._handle = ctypes.c_void_p()
+        r = len(relations)
+        descs = (RelationDesc * r)()
+        keep = []
+        for i, rel in enumerate(relations):
+            attrs = np.ascontiguousarray(np.asarray(rel.key_attrs, dtype=np.int32))
+            keys = np.ascontiguousarray(np.asarray(rel.keys))
+            if keys.dtype not in (np.int32, np.int64):
+                keys = keys.astype(np.int64)
+            keep += [attrs, keys]
+            descs[i].rows = int(rel.values.shape[1]) if hasattr(rel, "values") else int(keys.shape[1])
+            descs[i].num_keys = len(rel.key_attrs)
+            descs[i].key_attr = attrs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            descs[i].key_cols = ctypes.c_void_p(keys.ctypes.data if keys.size else 0)
+            descs[i].key_dtype = 8 if keys.dtype == np.int64 else 4
+            descs[i].num_cols = int(rel.values.shape[0]) if hasattr(rel, "values") else int(rel.ncols)
+            descs[i].parent = int(rel.parent)
+        opts = PlanOptions(tile_items, waves_per_task, 1, 1)
+        st = L.figaro_plan_create(ctypes.byref(self._handle), r, descs, ctypes.byref(opts), None)
+        if st != FIGARO_OK:
+            msg = L.figaro_last_error(None)
+            raise FigaroError(st, msg.decode() if msg else "")
+        self.r = r
+        self.n = L.figaro_plan_num_cols(self._handle)
+        self.ncols = [int(descs[i].num_cols) for i in range(r)]
+
+    # -- info ---------------------------------------------------------------
+    def rows(self, i: int) -> int:
+        return int(lib().figaro_plan_rows(self._handle, i))
+
+    def input_rows(self, i: int) -> int:
+        return int(lib().figaro_plan_input_rows(self._handle, i))
+
+    def dropped_rows(self, i: int) -> int:
+        return int(lib().figaro_plan_dropped_rows(self._handle, i))
+
+    @property
+    def join_rows(self) -> float:
+        return float(lib().figaro_plan_join_rows(self._handle))
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().figaro_plan_workspace_bytes(self._handle))
+
+    def permutation(self, i: int) -> np.ndarray:
+        out = np.zeros(self.input_rows(i), dtype=np.int64)
+        _check(lib().figaro_plan_permutation(self._handle, i,
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               self._handle)
+        return out
+
+    def num_groups(self, i: int, which: int = 0) -> int:
+        return int(lib().figaro_plan_num_groups(self._handle, i, which))
+
+    def group_first_rows(self, i: int, which: int = 0) -> np.ndarray:
+        out = np.zeros(max(self.num_groups(i, which), 0), dtype=np.int64)
+        _check(lib().figaro_plan_group_first_rows(self._handle, i, which,
+                                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               self._handle)
+        return out
+
+    def counts(self, i: int, kind: str) -> np.ndarray:
+        which = 1 if kind in ("phi_up", "phi_down") else 0
+        out = np.zeros(max(self.num_groups(i, which), 0), dtype=np.int64)
+        _check(lib().figaro_plan_counts(self._handle, i, COUNT_KINDS[kind],
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
+               self._handle)
+        return out
+
+    # -- data movement ------------------------------------------------------
+    def to_plan_order(self, i: int, values, stream=None):
+        """(n_i, m_i) caller-order device tensor -> (n_i, kept rows) plan order."""
+        import torch
+        assert values.dtype == torch.float64 and values.is_cuda and values.stride(1) == 1
+        out = torch.empty((values.shape[0], self.rows(i)), dtype=torch.float64, device=values.device)
+        _check(lib().figaro_permute_values(self._handle, i, ctypes.c_void_p(values.data_ptr()),
+                                           values.stride(0), ctypes.c_void_p(out.data_ptr()),
+                                           max(out.stride(0), 1), _stream_handle(stream)), self._handle)
+        return out
+
+    def from_plan_order(self, i: int, values, stream=None):
+        """(n_i, kept rows) plan-order tensor -> (n_i, m_i) caller order, zeros
+        for rows removed by the reduction."""
+        import torch
+        out = torch.empty((values.shape[0], self.input_rows(i)), dtype=torch.float64, device=values.device)
+        _check(lib().figaro_unpermute_values(self._handle, i, ctypes.c_void_p(values.data_ptr()),
+                                             max(values.stride(0), 1), ctypes.c_void_p(out.data_ptr()),
+                                             max(out.stride(0), 1), _stream_handle(stream)), self._handle)
+        return out
+
+    def _value_args(self, values):
+        import torch
+        if len(values) != self.r:
+            raise ValueError("one value tensor per relation")
+        ptrs = (ctypes.c_void_p * self.r)()
+        lds = (ctypes.c_int64 * self.r)()
+        for i, v in enumerate(values):
+            if v.dtype != torch.float64 or not v.is_cuda or v.stride(1) != 1:
+                raise ValueError("values must be float64 device tensors of shape (n_i, rows), rows contiguous")
+            if v.shape[0] != self.ncols[i] or v.shape[1] < self.rows(i):
+                raise ValueError(f"values[{i}] has shape {tuple(v.shape)}")
+            ptrs[i] = v.data_ptr()
+            lds[i] = max(v.stride(0), self.rows(i))
+        return ptrs, lds
+
+    # -- compute ------------------------------------------------------------
+    def r_factor(self, values: List, out=None, stream=None):
+        """R (n x n, upper triangular, non-negative diagonal) of the join."""
+        import torch
+        ptrs, lds = self._value_args(values)
+        if out is None:
+            out = torch.empty((self.n, self.n), dtype=torch.float64, device=values[0].device)
+        # column-major n x n == row-major transpose: allocate (n, n) and read .T
+        _check(lib().figaro_r(self._handle, ptrs, lds, ctypes.c_void_p(out.data_ptr()),
+                              _stream_handle(stream)), self._handle)
+        return out.T
+
+    def r0(self, values: List, stream=None):
+        """The intermediate R0 (rows x n) and the block id of every row."""
+        import torch
+        ptrs, lds = self._value_args(values)
+        rows = int(lib().figaro_r0_rows(self._handle))
+        buf = torch.empty((self.n, max(rows, 1)), dtype=torch.float64, device=values[0].device)
+        blk = torch.empty((max(rows, 1),), dtype=torch.int32, device=values[0].device)
+        _check(lib().figaro_r0(self._handle, ptrs, lds, ctypes.c_void_p(buf.data_ptr()), max(rows, 1),
+                               ctypes.c_void_p(blk.data_ptr()), _stream_handle(stream)), self._handle)
+        return buf[:, :rows].T, blk[:rows]
+
+    def debug_stack(self, values, stream=None):
+        """Partial R factors and root rows before the post-processing TSQR."""
+        ptrs, lds = self._value_args(values)
+        rows = int(lib().figaro_debug_stack_rows(self._handle))
+        out = np.zeros((self.n, max(rows, 1)), dtype=np.float64)
+        _check(lib().figaro_debug_stack(self._handle, ptrs, lds, ctypes.c_void_p(out.ctypes.data),
+                                        _stream_handle(stream)), self._handle)
+        return out[:, :rows].T
+
+    # -- profiling ------------------------------------------------------------
+    PROFILE_CLASSES = {0: "heads_tails", 1: "project_away", 2: "upper_levels", 3: "join",
+                       4: "root", 5: "post_tsqr", 6: "backward"}
+
+    def profile_enable(self, capacity: int = 4096):
+        _check(lib().figaro_profile_enable(self._handle, capacity), self._handle)
+
+    def profile_reset(self):
+        _check(lib().figaro_profile_reset(self._handle), self._handle)
+
+    def profile_read(self):
+        """{class name: (total ms, launches, algorithmic bytes, flops)}"""
+        out = {}
+        for k, name in self.PROFILE_CLASSES.items():
+            ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            _check(lib().figaro_profile_read(self._handle, k, ctypes.byref(ms), ctypes.byref(n),
+                                             ctypes.byref(b), ctypes.byref(f)), self._handle)
+            out[name] = (ms.value, n.value, b.value, f.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            lib().figaro_plan_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _RelView:
+    def __init__(self, key_attrs, keys, ncols, parent):
+        self.key_attrs = key_attrs
+        self.keys = keys
+        self.ncols = ncols
+        self.parent = parent
+
+
+def plan_from_instance(inst, device="cuda", **kw) -> Plan:
+    """Plan for a synth.Instance-like object (keys moved to the device)."""
+    import torch
+    rels = []
+    for rel in inst.rels:
+        keys = torch.as_tensor(np.ascontiguousarray(rel.keys)).to(device)
+        if keys.dim() == 1:
+            keys = keys[None, :]
+        rels.append(_RelView(list(rel.key_attrs), keys, rel.values.shape[0], rel.parent))
+    return Plan(rels, **kw)
+
+
+def device_values(plan: Plan, inst, device="cuda") -> List:
+    """Caller-order values of an instance -> plan-order device tensors."""
+    import torch
+    out = []
+    for i, rel in enumerate(inst.rels):
+        v = torch.as_tensor(np.ascontiguousarray(rel.values, dtype=np.float64)).to(device)
+        out.append(plan.to_plan_order(i, v))
+    return out

@@ -1,0 +1,246 @@
+// Internal structures shared by the plan builder, the launch sequence and the
+// kernels.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/figaro.h"
+
+namespace figaro {
+
+// Widest column count the register-tile kernels handle.
+constexpr int kMaxCols = 64;
+
+// ---------------------------------------------------------------------------
+// Kernel argument blocks (passed by value).
+// ---------------------------------------------------------------------------
+
+// One launch of the segmented head/tail + QR-accumulate kernel.
+//
+// Items are rows of `in` (column-major [ncols][ld_in]).  Each item has a
+// count c (1 for input rows) and a vector of column sums s.  Items are
+// grouped into pieces (consecutive items of one key group inside one chunk).
+// For the t-th item of a piece with W items' worth of count before it and
+// P the sum of the s of those items, the tail row is
+//     (W s - c P) / (sqrt(c) sqrt(W) sqrt(W + c)) * phi      (phi: group scale)
+// which is the generalized tail of Definition 2 written with sums instead of
+// heads.  The first item of a piece has no tail.  The kernel writes the sum
+// of every piece to `pieces_out` and either folds the tail rows into a
+// per-wave Householder R (mode FUSE) or writes them to an R0 buffer.
+struct HelmertArgs {
+    const double *in;
+    int64_t ld_in;
+    int32_t ncols;
+    int64_t items;
+    const int32_t *pid;          // [items] piece id of each item
+    const int64_t *piece_start;  // [npieces+1] first item of every piece
+    const double *phi_piece;     // unit-count mode: tail scale of every piece
+    const double *alpha;         // weighted mode: per-item tail coefficient of s
+    const double *beta;          // weighted mode: per-item tail coefficient of P
+    const int64_t *chunk_start;  // [nchunks+1]
+    int64_t nchunks;
+    double *pieces_out;          // [ncols][ld_pieces] (may be null: no piece output)
+    int64_t ld_pieces;
+    // QR output: each wave writes its R (ncols rows, n_total columns) at rows
+    // stack_row0 + wave*ncols of `stack`.
+    double *stack;
+    int64_t ld_stack;
+    int64_t stack_row0;
+    int32_t n_total;
+    const int32_t *inv_colmap;   // [n_total]: local column of a global column, or -1
+    const int32_t *colmap;       // [ncols]: global column of a local column
+    // R0 output (materialisation for inspection)
+    double *r0;
+    int64_t ld_r0;
+    int64_t r0_row0;
+    int32_t *block_of_row;
+    int32_t block_id;
+    int32_t waves;
+};
+
+// Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); each wave writes its
+// R (n rows) to `out` rows wave*n, or the final R (sign-normalised) to
+// `final_r` when waves == 1.
+struct DenseArgs {
+    const double *in;
+    int64_t ld_in;
+    int64_t rows;
+    int32_t n;
+    double *out;
+    int64_t ld_out;
+    int32_t waves;
+    int64_t tiles_per_wave;
+    double *final_r;
+};
+
+constexpr int kMaxChildren = 16;
+
+// process_and_join_children: per key group g of relation i,
+//   s[own columns][g]   = own_sum[g] * own_mult[g]
+//   s[child j cols][g]  = sigma_j[cidx_j[g]] * mult_j[g]
+struct JoinArgs {
+    int64_t groups;
+    int32_t nsub;
+    double *s;
+    int64_t ld_s;
+    const double *own;
+    int64_t ld_own;
+    int32_t own_cols;
+    int32_t own_pos;
+    const double *own_mult;
+    int32_t nchildren;
+    const double *sigma[kMaxChildren];
+    int64_t ld_sigma[kMaxChildren];
+    int32_t child_cols[kMaxChildren];
+    const int32_t *colpos[kMaxChildren];
+    const int32_t *cidx[kMaxChildren];
+    const double *mult[kMaxChildren];
+};
+
+// Root emit: rows s[.][g] / sqrt(c_g) into the stack (or R0).
+struct RootArgs {
+    int64_t groups;
+    int32_t n;
+    const double *s;
+    int64_t ld_s;
+    const double *inv_sqrt_c;    // [groups] (may be null: factor 1)
+    double *dst;
+    int64_t ld_dst;
+    int64_t row0;
+    int32_t *block_of_row;
+    int32_t block_id;
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s);
+hipError_t launch_dense(const DenseArgs &a, hipStream_t s);
+hipError_t launch_join(const JoinArgs &a, hipStream_t s);
+hipError_t launch_root(const RootArgs &a, bool to_r0, hipStream_t s);
+hipError_t launch_permute(const double *src, int64_t ld_src, double *dst, int64_t ld_dst,
+                          const int64_t *perm, int64_t rows, int32_t ncols, bool inverse,
+                          int64_t total_rows, hipStream_t s);
+hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+int tile_items_for(int ncols);        // items per chunk of the register-tile kernel
+int dense_tile_rows_for(int ncols);   // rows per tile of the dense kernel
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+
+// One level of a segmented head/tail task.
+struct Level {
+    int64_t items = 0, npieces = 0, nchunks = 0;
+    bool unit = false;
+    int32_t waves = 0;
+    int64_t stack_row0 = 0;       // first stack row of this launch's R's
+    int64_t r0_row0 = 0;          // first R0 row of this level
+    int32_t *d_pid = nullptr;
+    int64_t *d_piece_start = nullptr;
+    int64_t *d_chunk_start = nullptr;
+    double *d_phi_piece = nullptr;
+    double *d_alpha = nullptr, *d_beta = nullptr;
+    double *d_pieces = nullptr;   // [ncols][npieces]
+};
+
+// heads_and_tails (A2) or project_away_join_attributes (A4) of one relation.
+struct Task {
+    bool active = false;
+    int32_t ncols = 0;
+    int32_t block_id = 0;
+    std::vector<int32_t> cols;    // global columns, ascending
+    int32_t *d_colmap = nullptr;
+    int32_t *d_inv_colmap = nullptr;
+    std::vector<Level> levels;
+};
+
+struct RelPlan {
+    // as given
+    int64_t m_in = 0;
+    int32_t nkeys = 0;
+    std::vector<int32_t> attrs;   // as given
+    int32_t ncols = 0;
+    int32_t parent = -1;
+    std::vector<int32_t> children;
+    int32_t col0 = 0;             // first global column
+    // reduction, order, groups
+    int64_t m = 0;                // rows kept
+    std::vector<int64_t> perm;    // plan row -> caller row (kept rows first)
+    int64_t *d_perm = nullptr;
+    int64_t G = 0, P = 0;         // key groups, parent groups
+    std::vector<int64_t> seg_off; // [G+1] row offsets of key groups
+    std::vector<int64_t> par_off; // [P+1] key-group offsets of parent groups
+    // counts (exact)
+    std::vector<int64_t> rpk, theta, phi_circ, fjs;  // [G]
+    std::vector<int64_t> phi_up, phi_down;           // [P]
+    // heads/tails of S_i
+    bool singleton = false;       // every key group has one row
+    Task a2;
+    // join with children
+    int32_t nsub = 0;
+    std::vector<int32_t> sub_cols;   // global columns of the subtree, ascending
+    int32_t own_pos = 0;
+    double *d_own_mult = nullptr;
+    std::vector<int32_t *> d_cidx;
+    std::vector<double *> d_mult;
+    std::vector<int32_t *> d_colpos;
+    double *d_s = nullptr;           // [nsub][G]
+    // projection onto X_p
+    Task a4;
+    // root
+    double *d_inv_sqrt_c = nullptr;
+    int64_t root_row0 = 0;
+    int64_t r0_root_row0 = 0;
+};
+
+constexpr int kProfClasses = 8;
+
+struct ProfPending {
+    int kind;
+    int slot;
+    double bytes, flops;
+};
+
+struct DenseLevel {
+    int64_t rows;
+    int32_t waves;
+    int64_t tiles_per_wave;
+};
+
+}  // namespace figaro
+
+struct figaro_plan_s {
+    int32_t r = 0;
+    int32_t n = 0;
+    int32_t root = -1;
+    std::vector<int32_t> post;           // post-order of relations
+    std::vector<figaro::RelPlan> rel;
+    double join_rows = 0.0;
+    int device = 0;
+    int32_t tile_items = 0;
+    int32_t waves_cap = 0;
+    bool analyze_only = false;
+    // stack for the post-processing TSQR
+    int64_t stack_rows = 0;
+    double *d_stack[2] = {nullptr, nullptr};
+    int64_t stack_ld[2] = {0, 0};
+    std::vector<figaro::DenseLevel> dense;
+    int64_t r0_rows = 0;
+    int64_t workspace_bytes = 0;
+    std::vector<void *> allocations;
+    std::string last_error;
+    // profiling
+    std::vector<hipEvent_t> prof_start, prof_stop;
+    size_t prof_next = 0;
+    std::vector<figaro::ProfPending> prof_pending;
+    double prof_ms[figaro::kProfClasses] = {0};
+    int64_t prof_launches[figaro::kProfClasses] = {0};
+    double prof_bytes[figaro::kProfClasses] = {0};
+    double prof_flops[figaro::kProfClasses] = {0};
+};

@@ -1,0 +1,789 @@
+// Plan construction: everything that depends on the keys only.
+//
+//  * validation of the join tree (single root, connected, running
+//    intersection, every key attribute shared with a neighbour);
+//  * semi-join reduction of dangling tuples (the paper assumes a fully
+//    reduced database; a bottom-up then top-down pass of semi-joins over the
+//    join tree produces one);
+//  * the sort order both of the paper's algorithms assume: each relation
+//    sorted on the attributes it shares with its parent, then on its other
+//    key attributes (ties by row index);
+//  * the count queries of Fig. 4 by Algorithm 2 (bottom-up pass computing
+//    rows_per_key, Theta_down and Phi_down, top-down pass computing
+//    full_join_size, Phi_up and Phi_circ), exactly, in 64-bit integers;
+//  * the scale factors of Algorithm 3, and the tables of the segmented
+//    head/tail kernels (pieces, chunks, tail coefficients);
+//  * the device workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using u128 = unsigned __int128;
+
+namespace figaro {
+
+thread_local std::string g_thread_error;
+
+figaro_status set_error(figaro_plan_s *p, figaro_status st, const std::string &msg) {
+    if (p) p->last_error = msg;
+    g_thread_error = msg;
+    return st;
+}
+
+namespace {
+
+constexpr int64_t kExactLimit = int64_t(1) << 53;   // counts must stay below 2^53
+
+struct Packer {
+    // packs the dense ids of a list of attributes (high bits first)
+    std::vector<int32_t> attrs;   // global attribute ids, in packing order
+    std::vector<int> shift;
+    int bits = 0;
+};
+
+template <typename T>
+hipError_t dev_upload(figaro_plan_s *p, T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    size_t bytes = sizeof(T) * std::max<size_t>(src.size(), 1);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    p->allocations.push_back(*dst);
+    p->workspace_bytes += (int64_t)bytes;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t dev_alloc(figaro_plan_s *p, void **dst, size_t bytes) {
+    *dst = nullptr;
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return e;
+    p->allocations.push_back(*dst);
+    p->workspace_bytes += (int64_t)std::max<size_t>(bytes, 8);
+    return e;
+}
+
+struct Builder {
+    figaro_plan_s *p;
+    int32_t r;
+    std::vector<std::vector<int64_t>> keys;     // per relation [k][m] raw keys
+    std::vector<std::vector<int32_t>> ids;      // per relation [k][m] dense ids
+    std::vector<int> attr_bits;                 // per attribute id (dense index)
+    std::vector<int32_t> attr_list;             // distinct attribute ids
+    std::vector<std::vector<char>> alive;
+
+    int attr_index(int32_t a) const {
+        auto it = std::lower_bound(attr_list.begin(), attr_list.end(), a);
+        return int(it - attr_list.begin());
+    }
+    int key_pos(int i, int32_t a) const {
+        const auto &at = p->rel[i].attrs;
+        for (size_t q = 0; q < at.size(); ++q)
+            if (at[q] == a) return int(q);
+        return -1;
+    }
+    std::vector<int32_t> shared(int i, int j) const {
+        std::vector<int32_t> out;
+        for (int32_t a : p->rel[i].attrs)
+            if (key_pos(j, a) >= 0) out.push_back(a);
+        std::sort(out.begin(), out.end());
+        return out;
+    }
+    Packer make_packer(const std::vector<int32_t> &attrs) const {
+        Packer pk;
+        pk.attrs = attrs;
+        int total = 0;
+        for (int32_t a : attrs) total += attr_bits[attr_index(a)];
+        pk.bits = total;
+        int s = total;
+        for (int32_t a : attrs) {
+            s -= attr_bits[attr_index(a)];
+            pk.shift.push_back(s);
+        }
+        return pk;
+    }
+    u128 pack(int i, int64_t row, const Packer &pk) const {
+        u128 v = 0;
+        for (size_t q = 0; q < pk.attrs.size(); ++q) {
+            int kp = key_pos(i, pk.attrs[q]);
+            v |= (u128)(uint32_t)ids[i][(size_t)kp * p->rel[i].m_in + row] << pk.shift[q];
+        }
+        return v;
+    }
+};
+
+void postorder(const figaro_plan_s *p, int v, std::vector<int32_t> &out) {
+    for (int c : p->rel[v].children) postorder(p, c, out);
+    out.push_back(v);
+}
+
+// Build the levels of one segmented head/tail task.
+//   group_off: [ngroups+1] item offsets of the groups (level 0)
+//   counts   : per-item counts (empty = every item counts 1, unit level 0)
+//   phi      : per-group tail scale
+figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::vector<int64_t> &group_off,
+                         const std::vector<int64_t> &counts, const std::vector<double> &phi, int tile) {
+    const int64_t ngroups = (int64_t)group_off.size() - 1;
+    // level state
+    std::vector<int64_t> goff = group_off;      // group offsets over this level's items
+    std::vector<int64_t> cnt = counts;          // per item counts (empty: all 1)
+    int64_t nitems = items;
+    bool unit = counts.empty();
+    for (int level = 0; level < 64; ++level) {
+        Level L;
+        L.items = nitems;
+        L.unit = unit;
+        // chunks
+        std::vector<int64_t> cs;
+        cs.push_back(0);
+        if (level == 0) {
+            for (int64_t s = tile; s < nitems; s += tile) cs.push_back(s);
+            cs.push_back(nitems);
+        } else {
+            int64_t cur = 0;       // items in the current chunk
+            for (int64_t g = 0; g < ngroups; ++g) {
+                int64_t gs = goff[g], ge = goff[g + 1], sz = ge - gs;
+                if (sz > tile) {
+                    if (cur > 0) { cs.push_back(gs); cur = 0; }
+                    for (int64_t s = gs + tile; s < ge; s += tile) cs.push_back(s);
+                    cs.push_back(ge);
+                    cur = 0;
+                } else {
+                    if (cur + sz > tile) { cs.push_back(gs); cur = 0; }
+                    cur += sz;
+                }
+            }
+            if (cs.back() != nitems) cs.push_back(nitems);
+        }
+        L.nchunks = (int64_t)cs.size() - 1;
+        // pieces: chunk x group intersections
+        std::vector<int32_t> pid(nitems);
+        std::vector<int64_t> pstart;
+        std::vector<int64_t> pgroup;
+        std::vector<int64_t> pcount;
+        int64_t g = 0;
+        for (int64_t c = 0; c < L.nchunks; ++c) {
+            int64_t a = cs[c], b = cs[c + 1];
+            int64_t t = a;
+            while (t < b) {
+                while (goff[g + 1] <= t) ++g;
+                int64_t e = std::min(b, goff[g + 1]);
+                int64_t idx = (int64_t)pstart.size();
+                pstart.push_back(t);
+                pgroup.push_back(g);
+                int64_t sum = 0;
+                for (int64_t q = t; q < e; ++q) {
+                    pid[q] = (int32_t)idx;
+                    sum += unit ? 1 : cnt[q];
+                }
+                pcount.push_back(sum);
+                t = e;
+            }
+        }
+        L.npieces = (int64_t)pstart.size();
+        if (L.npieces >= (int64_t(1) << 31))
+            return set_error(p, FIGARO_EUNSUPPORTED, "too many pieces in one head/tail level");
+        pstart.push_back(nitems);
+        hipError_t e;
+        if ((e = dev_upload(p, &L.d_pid, pid)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        if ((e = dev_upload(p, &L.d_piece_start, pstart)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        if ((e = dev_upload(p, &L.d_chunk_start, cs)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        if (unit) {
+            std::vector<double> pp(L.npieces);
+            for (int64_t q = 0; q < L.npieces; ++q) pp[q] = phi[pgroup[q]];
+            if (dev_upload(p, &L.d_phi_piece, pp) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        } else {
+            std::vector<double> al(nitems), be(nitems);
+            for (int64_t q = 0; q < L.npieces; ++q) {
+                int64_t W = 0;
+                double ph = phi[pgroup[q]];
+                for (int64_t t = pstart[q]; t < pstart[q + 1]; ++t) {
+                    int64_t c = cnt[t];
+                    if (W == 0) {
+                        al[t] = 0.0;
+                        be[t] = 0.0;
+                    } else {
+                        double sW = std::sqrt((double)W), sc = std::sqrt((double)c),
+                               sWi = std::sqrt((double)(W + c));
+                        al[t] = ph * sW / (sc * sWi);
+                        be[t] = ph * sc / (sW * sWi);
+                    }
+                    W += c;
+                }
+            }
+            if (dev_upload(p, &L.d_alpha, al) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            if (dev_upload(p, &L.d_beta, be) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        }
+        if (dev_alloc(p, (void **)&L.d_pieces, sizeof(double) * (size_t)T.ncols * (size_t)L.npieces) != hipSuccess)
+            return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        L.waves = (int32_t)std::min<int64_t>(L.nchunks, p->waves_cap);
+        if (L.waves < 1) L.waves = 1;
+        T.levels.push_back(L);
+        if (L.npieces == ngroups) return FIGARO_OK;
+        // next level: items are the pieces
+        std::vector<int64_t> ngoff(ngroups + 1, 0);
+        for (int64_t q = 0; q < L.npieces; ++q) ngoff[pgroup[q] + 1]++;
+        for (int64_t q = 0; q < ngroups; ++q) ngoff[q + 1] += ngoff[q];
+        goff = ngoff;
+        cnt = pcount;
+        nitems = L.npieces;
+        unit = false;
+    }
+    return set_error(p, FIGARO_EUNSUPPORTED, "head/tail levels do not converge");
+}
+
+figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total) {
+    std::vector<int32_t> inv(n_total, -1);
+    for (size_t q = 0; q < T.cols.size(); ++q) inv[T.cols[q]] = (int32_t)q;
+    if (dev_upload(p, &T.d_colmap, T.cols) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+    if (dev_upload(p, &T.d_inv_colmap, inv) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+    return FIGARO_OK;
+}
+
+figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rels,
+                    const figaro_plan_options *opts, hipStream_t stream) {
+    Builder B;
+    B.p = p;
+    B.r = r;
+    p->r = r;
+    p->rel.resize(r);
+    p->tile_items = opts ? opts->tile_items : 0;
+    p->waves_cap = (opts && opts->waves_per_task > 0) ? opts->waves_per_task : 2048;
+    const bool keys_on_host = opts && opts->keys_on_host;
+    p->analyze_only = opts && opts->analyze_only;
+    if (p->tile_items < 0) return set_error(p, FIGARO_EINVAL, "tile_items must be >= 0");
+    // ---- argument checks
+    int roots = 0;
+    for (int i = 0; i < r; ++i) {
+        const auto &d = rels[i];
+        auto &R = p->rel[i];
+        if (d.rows < 0) return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": rows < 0");
+        if (d.num_keys < 0 || d.num_keys > 32)
+            return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": num_keys out of range");
+        if (d.num_keys > 0 && (d.key_attr == nullptr || (d.key_cols == nullptr && d.rows > 0)))
+            return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": null key pointer");
+        if (d.num_keys > 0 && d.key_dtype != 4 && d.key_dtype != 8)
+            return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": key_dtype must be 4 or 8");
+        if (d.num_cols < 1) return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": num_cols < 1");
+        if (d.parent < -1 || d.parent >= r || d.parent == i)
+            return set_error(p, FIGARO_ENOTTREE, "relation " + std::to_string(i) + ": parent out of range");
+        if (d.parent == -1) { ++roots; p->root = i; }
+        R.m_in = d.rows;
+        R.nkeys = d.num_keys;
+        R.attrs.assign(d.key_attr, d.key_attr + d.num_keys);
+        R.ncols = d.num_cols;
+        R.parent = d.parent;
+        for (int a = 0; a < d.num_keys; ++a)
+            for (int b = a + 1; b < d.num_keys; ++b)
+                if (R.attrs[a] == R.attrs[b])
+                    return set_error(p, FIGARO_EINVAL, "relation " + std::to_string(i) + ": repeated key attribute");
+    }
+    if (roots != 1) return set_error(p, FIGARO_ENOTTREE, "the join tree must have exactly one root");
+    for (int i = 0; i < r; ++i)
+        if (p->rel[i].parent >= 0) p->rel[p->rel[i].parent].children.push_back(i);
+    {
+        // connected from the root (each node has one parent, so reachability of all nodes == tree)
+        std::vector<char> seen(r, 0);
+        std::vector<int> st{p->root};
+        int cnt = 0;
+        while (!st.empty()) {
+            int v = st.back();
+            st.pop_back();
+            if (seen[v]) return set_error(p, FIGARO_ENOTTREE, "cycle in parent links");
+            seen[v] = 1;
+            ++cnt;
+            for (int c : p->rel[v].children) st.push_back(c);
+        }
+        if (cnt != r) return set_error(p, FIGARO_ENOTTREE, "parent links do not form one tree");
+    }
+    postorder(p, p->root, p->post);
+    // running intersection and shared keys
+    {
+        std::vector<int32_t> all;
+        for (int i = 0; i < r; ++i) all.insert(all.end(), p->rel[i].attrs.begin(), p->rel[i].attrs.end());
+        std::sort(all.begin(), all.end());
+        all.erase(std::unique(all.begin(), all.end()), all.end());
+        B.attr_list = all;
+        for (int32_t a : all) {
+            int nodes = 0, edges = 0;
+            for (int i = 0; i < r; ++i) {
+                if (B.key_pos(i, a) < 0) continue;
+                ++nodes;
+                int pp = p->rel[i].parent;
+                if (pp >= 0 && B.key_pos(pp, a) >= 0) ++edges;
+            }
+            if (edges != nodes - 1)
+                return set_error(p, FIGARO_ENOTTREE,
+                                 "attribute " + std::to_string(a) + " violates the running intersection property");
+        }
+        for (int i = 0; i < r; ++i)
+            for (int32_t a : p->rel[i].attrs) {
+                bool ok = p->rel[i].parent >= 0 && B.key_pos(p->rel[i].parent, a) >= 0;
+                for (int c : p->rel[i].children) ok = ok || B.key_pos(c, a) >= 0;
+                if (!ok)
+                    return set_error(p, FIGARO_EUNSHARED_KEY, "relation " + std::to_string(i) + ": key attribute " +
+                                                                  std::to_string(a) + " is shared with no neighbour");
+            }
+    }
+    // columns
+    int32_t n = 0;
+    for (int i = 0; i < r; ++i) {
+        p->rel[i].col0 = n;
+        n += p->rel[i].ncols;
+    }
+    p->n = n;
+    if (n > kMaxCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 64 data columns in total");
+    // ---- keys to the host
+    B.keys.resize(r);
+    for (int i = 0; i < r; ++i) {
+        const auto &d = rels[i];
+        size_t cnt = (size_t)d.num_keys * (size_t)d.rows;
+        B.keys[i].resize(cnt);
+        if (cnt == 0) continue;
+        if (keys_on_host) {
+            if (d.key_dtype == 8) {
+                std::memcpy(B.keys[i].data(), d.key_cols, cnt * 8);
+            } else {
+                const int32_t *src = (const int32_t *)d.key_cols;
+                for (size_t q = 0; q < cnt; ++q) B.keys[i][q] = src[q];
+            }
+        } else if (d.key_dtype == 8) {
+            if (hipMemcpyAsync(B.keys[i].data(), d.key_cols, cnt * 8, hipMemcpyDeviceToHost, stream) != hipSuccess)
+                return set_error(p, FIGARO_EHIP, "copying key columns to the host failed");
+        } else {
+            std::vector<int32_t> tmp(cnt);
+            if (hipMemcpyAsync(tmp.data(), d.key_cols, cnt * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess)
+                return set_error(p, FIGARO_EHIP, "copying key columns to the host failed");
+            for (size_t q = 0; q < cnt; ++q) B.keys[i][q] = tmp[q];
+        }
+    }
+    if (!keys_on_host && hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(p, FIGARO_EHIP, "hipStreamSynchronize failed");
+    // ---- dictionary-encode every attribute
+    B.attr_bits.assign(B.attr_list.size(), 1);
+    B.ids.resize(r);
+    for (int i = 0; i < r; ++i) B.ids[i].resize(B.keys[i].size());
+    for (size_t ai = 0; ai < B.attr_list.size(); ++ai) {
+        int32_t a = B.attr_list[ai];
+        std::vector<int64_t> vals;
+        for (int i = 0; i < r; ++i) {
+            int kp = B.key_pos(i, a);
+            if (kp < 0) continue;
+            const int64_t *col = B.keys[i].data() + (size_t)kp * p->rel[i].m_in;
+            vals.insert(vals.end(), col, col + p->rel[i].m_in);
+        }
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        int bits = 1;
+        while ((int64_t(1) << bits) < (int64_t)vals.size()) ++bits;
+        B.attr_bits[ai] = bits;
+        for (int i = 0; i < r; ++i) {
+            int kp = B.key_pos(i, a);
+            if (kp < 0) continue;
+            const int64_t *col = B.keys[i].data() + (size_t)kp * p->rel[i].m_in;
+            int32_t *out = B.ids[i].data() + (size_t)kp * p->rel[i].m_in;
+            for (int64_t t = 0; t < p->rel[i].m_in; ++t)
+                out[t] = (int32_t)(std::lower_bound(vals.begin(), vals.end(), col[t]) - vals.begin());
+        }
+    }
+    for (int i = 0; i < r; ++i) {
+        Packer pk = B.make_packer(p->rel[i].attrs);
+        if (pk.bits > 127)
+            return set_error(p, FIGARO_EUNSUPPORTED, "composite key of relation " + std::to_string(i) +
+                                                         " needs more than 127 bits");
+    }
+    // ---- semi-join reduction (bottom-up, then top-down)
+    B.alive.resize(r);
+    for (int i = 0; i < r; ++i) B.alive[i].assign(p->rel[i].m_in, 1);
+    auto semijoin = [&](int keep_side, int probe_side) {
+        // keep rows of keep_side whose projection on the shared attributes
+        // occurs among the alive rows of probe_side
+        std::vector<int32_t> sh = B.shared(keep_side, probe_side);
+        Packer pk = B.make_packer(sh);
+        std::vector<u128> set;
+        set.reserve(p->rel[probe_side].m_in);
+        for (int64_t t = 0; t < p->rel[probe_side].m_in; ++t)
+            if (B.alive[probe_side][t]) set.push_back(B.pack(probe_side, t, pk));
+        std::sort(set.begin(), set.end());
+        set.erase(std::unique(set.begin(), set.end()), set.end());
+        for (int64_t t = 0; t < p->rel[keep_side].m_in; ++t)
+            if (B.alive[keep_side][t] && !std::binary_search(set.begin(), set.end(), B.pack(keep_side, t, pk)))
+                B.alive[keep_side][t] = 0;
+    };
+    for (int v : p->post)
+        if (p->rel[v].parent >= 0) semijoin(p->rel[v].parent, v);
+    for (auto it = p->post.rbegin(); it != p->post.rend(); ++it)
+        if (p->rel[*it].parent >= 0) semijoin(*it, p->rel[*it].parent);
+    for (int i = 0; i < r; ++i) {
+        int64_t m = 0;
+        for (int64_t t = 0; t < p->rel[i].m_in; ++t) m += B.alive[i][t];
+        p->rel[i].m = m;
+        if (m == 0) return set_error(p, FIGARO_EEMPTY_JOIN, "the join is empty");
+    }
+    // ---- sort, segment, parent groups
+    std::vector<Packer> xp_pack(r), full_pack(r);
+    std::vector<std::vector<u128>> pgroup_keys(r);
+    std::vector<std::vector<u128>> seg_keys(r);     // full packed key of each segment (xp high)
+    for (int i = 0; i < r; ++i) {
+        auto &R = p->rel[i];
+        std::vector<int32_t> xp = R.parent >= 0 ? B.shared(i, R.parent) : std::vector<int32_t>{};
+        std::vector<int32_t> rest;
+        for (int32_t a : R.attrs)
+            if (std::find(xp.begin(), xp.end(), a) == xp.end()) rest.push_back(a);
+        std::sort(rest.begin(), rest.end());
+        xp_pack[i] = B.make_packer(xp);
+        std::vector<int32_t> order = xp;
+        order.insert(order.end(), rest.begin(), rest.end());
+        full_pack[i] = B.make_packer(order);
+        const int rest_bits = full_pack[i].bits - xp_pack[i].bits;
+        std::vector<std::pair<u128, int64_t>> kv;
+        kv.reserve(R.m);
+        for (int64_t t = 0; t < R.m_in; ++t)
+            if (B.alive[i][t]) kv.emplace_back(B.pack(i, t, full_pack[i]), t);
+        std::sort(kv.begin(), kv.end());
+        R.perm.resize(R.m_in);
+        for (int64_t q = 0; q < R.m; ++q) R.perm[q] = kv[q].second;
+        int64_t q = R.m;
+        for (int64_t t = 0; t < R.m_in; ++t)
+            if (!B.alive[i][t]) R.perm[q++] = t;
+        R.seg_off.clear();
+        for (int64_t t = 0; t < R.m; ++t)
+            if (t == 0 || kv[t].first != kv[t - 1].first) {
+                R.seg_off.push_back(t);
+                seg_keys[i].push_back(kv[t].first);
+            }
+        R.seg_off.push_back(R.m);
+        R.G = (int64_t)R.seg_off.size() - 1;
+        R.par_off.clear();
+        if (R.parent >= 0) {
+            for (int64_t g = 0; g < R.G; ++g) {
+                u128 hi = rest_bits >= 128 ? (u128)0 : (seg_keys[i][g] >> rest_bits);
+                if (g == 0 || hi != pgroup_keys[i].back()) {
+                    R.par_off.push_back(g);
+                    pgroup_keys[i].push_back(hi);
+                }
+            }
+            R.par_off.push_back(R.G);
+            R.P = (int64_t)R.par_off.size() - 1;
+        } else {
+            R.P = 0;
+        }
+        R.singleton = (R.G == R.m);
+        if (!p->analyze_only && dev_upload(p, &R.d_perm, R.perm) != hipSuccess)
+            return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+    }
+    // ---- child index of every key group
+    std::vector<std::vector<std::vector<int32_t>>> cidx(r);
+    for (int i = 0; i < r; ++i) {
+        auto &R = p->rel[i];
+        for (int c : R.children) {
+            std::vector<int32_t> idx(R.G);
+            for (int64_t g = 0; g < R.G; ++g) {
+                int64_t row = R.perm[R.seg_off[g]];
+                u128 k = B.pack(i, row, xp_pack[c]);
+                auto &keys = pgroup_keys[c];
+                auto it = std::lower_bound(keys.begin(), keys.end(), k);
+                if (it == keys.end() || *it != k)
+                    return set_error(p, FIGARO_EINVAL, "internal: unmatched key after reduction");
+                idx[g] = (int32_t)(it - keys.begin());
+            }
+            cidx[i].push_back(idx);
+        }
+    }
+    // ---- count queries, Algorithm 2
+    auto check = [&](u128 v) { return v < (u128)kExactLimit; };
+    for (int v : p->post) {   // pass 1: bottom-up
+        auto &R = p->rel[v];
+        R.rpk.resize(R.G);
+        R.theta.resize(R.G);
+        for (int64_t g = 0; g < R.G; ++g) {
+            R.rpk[g] = R.seg_off[g + 1] - R.seg_off[g];
+            u128 th = (u128)R.rpk[g];
+            for (size_t c = 0; c < R.children.size(); ++c) {
+                th *= (u128)p->rel[R.children[c]].phi_down[cidx[v][c][g]];
+                if (!check(th)) return set_error(p, FIGARO_EOVERFLOW, "a count query reaches 2^53");
+            }
+            R.theta[g] = (int64_t)th;
+        }
+        if (R.parent >= 0) {
+            R.phi_down.assign(R.P, 0);
+            for (int64_t q = 0; q < R.P; ++q) {
+                u128 s = 0;
+                for (int64_t g = R.par_off[q]; g < R.par_off[q + 1]; ++g) s += (u128)R.theta[g];
+                if (!check(s)) return set_error(p, FIGARO_EOVERFLOW, "a count query reaches 2^53");
+                R.phi_down[q] = (int64_t)s;
+            }
+        }
+    }
+    {
+        u128 total = 0;
+        for (int64_t t : p->rel[p->root].theta) total += (u128)t;
+        if (!check(total)) return set_error(p, FIGARO_EOVERFLOW, "the join size reaches 2^53");
+        p->join_rows = (double)(int64_t)total;
+    }
+    for (auto it = p->post.rbegin(); it != p->post.rend(); ++it) {   // pass 2: top-down
+        int v = *it;
+        auto &R = p->rel[v];
+        R.fjs.resize(R.G);
+        R.phi_circ.resize(R.G);
+        std::vector<std::vector<u128>> acc(R.children.size());
+        for (size_t c = 0; c < R.children.size(); ++c) acc[c].assign(p->rel[R.children[c]].P, 0);
+        int64_t q = 0;
+        for (int64_t g = 0; g < R.G; ++g) {
+            u128 up = 1;
+            if (R.parent >= 0) {
+                while (R.par_off[q + 1] <= g) ++q;
+                up = (u128)R.phi_up[q];
+            }
+            u128 f = up * (u128)R.theta[g];
+            if (!check(f)) return set_error(p, FIGARO_EOVERFLOW, "a count query reaches 2^53");
+            R.fjs[g] = (int64_t)f;
+            for (size_t c = 0; c < R.children.size(); ++c) acc[c][cidx[v][c][g]] += f;
+            R.phi_circ[g] = (int64_t)(f / (u128)R.rpk[g]);
+        }
+        for (size_t c = 0; c < R.children.size(); ++c) {
+            auto &C = p->rel[R.children[c]];
+            C.phi_up.resize(C.P);
+            for (int64_t k = 0; k < C.P; ++k) {
+                if (acc[c][k] % (u128)C.phi_down[k] != 0)
+                    return set_error(p, FIGARO_EINVAL, "internal: inexact division in the count queries");
+                C.phi_up[k] = (int64_t)(acc[c][k] / (u128)C.phi_down[k]);
+            }
+        }
+    }
+    if (p->analyze_only) return FIGARO_OK;
+    // ---- subtree columns, scale factors, head/tail tasks
+    std::vector<std::vector<int32_t>> subtree_cols(r);
+    for (int v : p->post) {
+        auto &R = p->rel[v];
+        std::vector<int32_t> cols;
+        for (int c = 0; c < R.ncols; ++c) cols.push_back(R.col0 + c);
+        for (int c : R.children) cols.insert(cols.end(), subtree_cols[c].begin(), subtree_cols[c].end());
+        std::sort(cols.begin(), cols.end());
+        subtree_cols[v] = cols;
+        R.sub_cols = cols;
+        R.nsub = (int32_t)cols.size();
+        R.own_pos = (int32_t)(std::lower_bound(cols.begin(), cols.end(), R.col0) - cols.begin());
+    }
+    for (int v : p->post) {
+        auto &R = p->rel[v];
+        const int tile_a2 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.ncols)) : tile_items_for(R.ncols);
+        // heads_and_tails of S_v
+        if (!R.singleton) {
+            R.a2.active = true;
+            R.a2.ncols = R.ncols;
+            R.a2.block_id = 3 * v + 0;
+            for (int c = 0; c < R.ncols; ++c) R.a2.cols.push_back(R.col0 + c);
+            std::vector<double> phi(R.G);
+            for (int64_t g = 0; g < R.G; ++g) phi[g] = std::sqrt((double)R.phi_circ[g]);
+            figaro_status st = build_task(p, R.a2, R.m, R.seg_off, {}, phi, tile_a2);
+            if (st != FIGARO_OK) return st;
+            if ((st = finish_task(p, R.a2, n)) != FIGARO_OK) return st;
+        }
+        if (!R.children.empty()) {
+            std::vector<double> own(R.G);
+            std::vector<std::vector<double>> mult(R.children.size(), std::vector<double>(R.G));
+            for (int64_t g = 0; g < R.G; ++g) {
+                u128 prod = 1;
+                for (size_t c = 0; c < R.children.size(); ++c)
+                    prod *= (u128)p->rel[R.children[c]].phi_down[cidx[v][c][g]];
+                own[g] = (double)(int64_t)prod;
+                for (size_t c = 0; c < R.children.size(); ++c) {
+                    u128 m = (u128)R.rpk[g];
+                    for (size_t c2 = 0; c2 < R.children.size(); ++c2)
+                        if (c2 != c) m *= (u128)p->rel[R.children[c2]].phi_down[cidx[v][c2][g]];
+                    mult[c][g] = (double)(int64_t)m;
+                }
+            }
+            if (dev_upload(p, &R.d_own_mult, own) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            for (size_t c = 0; c < R.children.size(); ++c) {
+                int32_t *di;
+                double *dm;
+                int32_t *dp;
+                if (dev_upload(p, &di, cidx[v][c]) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                if (dev_upload(p, &dm, mult[c]) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                std::vector<int32_t> pos;
+                for (int32_t col : subtree_cols[R.children[c]])
+                    pos.push_back((int32_t)(std::lower_bound(R.sub_cols.begin(), R.sub_cols.end(), col) -
+                                            R.sub_cols.begin()));
+                if (dev_upload(p, &dp, pos) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                R.d_cidx.push_back(di);
+                R.d_mult.push_back(dm);
+                R.d_colpos.push_back(dp);
+            }
+            if (R.children.size() > (size_t)kMaxChildren)
+                return set_error(p, FIGARO_EUNSUPPORTED, "more than 16 children of one relation");
+            if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess)
+                return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            if (R.parent >= 0 && R.P < R.G) {
+                R.a4.active = true;
+                R.a4.ncols = R.nsub;
+                R.a4.block_id = 3 * v + 1;
+                R.a4.cols = R.sub_cols;
+                std::vector<double> phi(R.P);
+                for (int64_t q = 0; q < R.P; ++q) phi[q] = std::sqrt((double)R.phi_up[q]);
+                const int tile_a4 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.nsub)) : tile_items_for(R.nsub);
+                figaro_status st = build_task(p, R.a4, R.G, R.par_off, R.theta, phi, tile_a4);
+                if (st != FIGARO_OK) return st;
+                if ((st = finish_task(p, R.a4, n)) != FIGARO_OK) return st;
+            }
+        }
+        if (R.parent < 0) {
+            std::vector<double> isc(R.G);
+            for (int64_t g = 0; g < R.G; ++g) isc[g] = 1.0 / std::sqrt((double)R.theta[g]);
+            if (dev_upload(p, &R.d_inv_sqrt_c, isc) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        }
+    }
+    // ---- stack rows (fused R's of every launch, then the root rows) and R0 rows
+    int64_t srow = 0, r0row = 0;
+    for (int v : p->post) {
+        auto &R = p->rel[v];
+        for (Task *T : {&R.a2, &R.a4}) {
+            if (!T->active) continue;
+            for (auto &L : T->levels) {
+                L.stack_row0 = srow;
+                srow += (int64_t)L.waves * T->ncols;
+                L.r0_row0 = r0row;
+                r0row += L.items;
+            }
+        }
+        if (R.parent < 0) {
+            R.root_row0 = srow;
+            srow += R.G;
+            R.r0_root_row0 = r0row;
+            r0row += R.G;
+        }
+    }
+    p->stack_rows = srow;
+    p->r0_rows = r0row;
+    // dense TSQR levels over the stack
+    const int dt = dense_tile_rows_for(n);
+    int64_t rows = srow;
+    int64_t maxnext = 0;
+    while (true) {
+        DenseLevel D;
+        D.rows = rows;
+        if (rows <= 4 * (int64_t)dt) {
+            D.waves = 1;
+            D.tiles_per_wave = std::max<int64_t>(1, (rows + dt - 1) / dt);
+            p->dense.push_back(D);
+            break;
+        }
+        D.tiles_per_wave = 1;
+        D.waves = (int32_t)((rows + dt - 1) / dt);
+        p->dense.push_back(D);
+        rows = (int64_t)D.waves * n;
+        maxnext = std::max(maxnext, rows);
+    }
+    p->stack_ld[0] = std::max<int64_t>(srow, 1);
+    p->stack_ld[1] = std::max<int64_t>(maxnext, 1);
+    if (dev_alloc(p, (void **)&p->d_stack[0], sizeof(double) * (size_t)n * (size_t)p->stack_ld[0]) != hipSuccess ||
+        dev_alloc(p, (void **)&p->d_stack[1], sizeof(double) * (size_t)n * (size_t)p->stack_ld[1]) != hipSuccess)
+        return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+    return FIGARO_OK;
+}
+
+}  // namespace
+}  // namespace figaro
+
+using namespace figaro;
+
+extern "C" {
+
+figaro_status figaro_plan_create(figaro_plan_t *out, int32_t r, const figaro_relation_desc *rels,
+                                 const figaro_plan_options *opts, hipStream_t stream) {
+    if (!out) return set_error(nullptr, FIGARO_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (r < 1 || !rels) return set_error(nullptr, FIGARO_EINVAL, "need at least one relation");
+    figaro_plan_s *p = new figaro_plan_s();
+    if (!(opts && opts->keys_on_host && opts->analyze_only)) (void)hipGetDevice(&p->device);
+    figaro_status st;
+    try {
+        st = build(p, r, rels, opts, stream);
+    } catch (const std::bad_alloc &) {
+        st = set_error(p, FIGARO_ENOMEM, "host allocation failed");
+    } catch (...) {
+        st = set_error(p, FIGARO_EINVAL, "unexpected error while building the plan");
+    }
+    if (st != FIGARO_OK) {
+        std::string msg = p->last_error;
+        figaro_plan_destroy(p);
+        g_thread_error = msg;
+        return st;
+    }
+    *out = p;
+    return FIGARO_OK;
+}
+
+void figaro_plan_destroy(figaro_plan_t p) {
+    if (!p) return;
+    for (auto e : p->prof_start) (void)hipEventDestroy(e);
+    for (auto e : p->prof_stop) (void)hipEventDestroy(e);
+    for (void *a : p->allocations) (void)hipFree(a);
+    delete p;
+}
+
+int32_t figaro_plan_num_relations(figaro_plan_t p) { return p ? p->r : -1; }
+int32_t figaro_plan_num_cols(figaro_plan_t p) { return p ? p->n : -1; }
+int64_t figaro_plan_input_rows(figaro_plan_t p, int32_t i) {
+    return (p && i >= 0 && i < p->r) ? p->rel[i].m_in : -1;
+}
+int64_t figaro_plan_rows(figaro_plan_t p, int32_t i) { return (p && i >= 0 && i < p->r) ? p->rel[i].m : -1; }
+int64_t figaro_plan_dropped_rows(figaro_plan_t p, int32_t i) {
+    return (p && i >= 0 && i < p->r) ? p->rel[i].m_in - p->rel[i].m : -1;
+}
+double figaro_plan_join_rows(figaro_plan_t p) { return p ? p->join_rows : -1.0; }
+int64_t figaro_plan_workspace_bytes(figaro_plan_t p) { return p ? p->workspace_bytes : -1; }
+
+figaro_status figaro_plan_permutation(figaro_plan_t p, int32_t i, int64_t *perm) {
+    if (!p || i < 0 || i >= p->r || !perm) return set_error(p, FIGARO_EINVAL, "bad argument");
+    std::memcpy(perm, p->rel[i].perm.data(), sizeof(int64_t) * p->rel[i].perm.size());
+    return FIGARO_OK;
+}
+
+int64_t figaro_plan_num_groups(figaro_plan_t p, int32_t i, int32_t which) {
+    if (!p || i < 0 || i >= p->r) return -1;
+    return which == 0 ? p->rel[i].G : (which == 1 ? p->rel[i].P : -1);
+}
+
+figaro_status figaro_plan_group_first_rows(figaro_plan_t p, int32_t i, int32_t which, int64_t *out) {
+    if (!p || i < 0 || i >= p->r || !out || (which != 0 && which != 1))
+        return set_error(p, FIGARO_EINVAL, "bad argument");
+    const auto &R = p->rel[i];
+    if (which == 0) {
+        for (int64_t g = 0; g < R.G; ++g) out[g] = R.perm[R.seg_off[g]];
+    } else {
+        for (int64_t q = 0; q < R.P; ++q) out[q] = R.perm[R.seg_off[R.par_off[q]]];
+    }
+    return FIGARO_OK;
+}
+
+figaro_status figaro_plan_counts(figaro_plan_t p, int32_t i, figaro_count_kind kind, int64_t *out) {
+    if (!p || i < 0 || i >= p->r || !out) return set_error(p, FIGARO_EINVAL, "bad argument");
+    const auto &R = p->rel[i];
+    const std::vector<int64_t> *v = nullptr;
+    switch (kind) {
+        case FIGARO_COUNT_ROWS_PER_KEY: v = &R.rpk; break;
+        case FIGARO_COUNT_THETA_DOWN: v = &R.theta; break;
+        case FIGARO_COUNT_PHI_CIRC: v = &R.phi_circ; break;
+        case FIGARO_COUNT_PHI_UP: v = &R.phi_up; break;
+        case FIGARO_COUNT_PHI_DOWN: v = &R.phi_down; break;
+        default: return set_error(p, FIGARO_EINVAL, "unknown count kind");
+    }
+    if (R.parent < 0 && (kind == FIGARO_COUNT_PHI_UP || kind == FIGARO_COUNT_PHI_DOWN))
+        return set_error(p, FIGARO_EINVAL, "the root has no parent groups");
+    std::memcpy(out, v->data(), sizeof(int64_t) * v->size());
+    return FIGARO_OK;
+}
+
+const char *figaro_last_error(figaro_plan_t p) {
+    if (p) return p->last_error.c_str();
+    return g_thread_error.c_str();
+}
+
+}  // extern "C"

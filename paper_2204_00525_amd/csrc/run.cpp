@@ -1,0 +1,338 @@
+// Launch sequence of the forward pass: post-order over the join tree
+// (Algorithm 3), then the post-processing TSQR over the stack of partial R's.
+// Everything is enqueued on the caller's stream; nothing is allocated and the
+// host is never synchronised.
+#include <string>
+
+#include "internal.hpp"
+#include "../../include/figaro_debug.h"
+
+namespace figaro {
+figaro_status set_error(figaro_plan_s *p, figaro_status st, const std::string &msg);
+}
+
+using namespace figaro;
+
+namespace {
+
+#define FIGARO_TRY(expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return set_error(p, FIGARO_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Timing of one launch when profiling is enabled (no-op otherwise).
+struct ProfScope {
+    figaro_plan_s *p;
+    hipStream_t s;
+    int slot = -1;
+    int kind;
+    double bytes, flops;
+    ProfScope(figaro_plan_s *p_, hipStream_t s_, int kind_, double bytes_, double flops_)
+        : p(p_), s(s_), kind(kind_), bytes(bytes_), flops(flops_) {
+        if (p->prof_next < p->prof_start.size()) {
+            slot = (int)p->prof_next++;
+            if (hipEventRecord(p->prof_start[slot], s) != hipSuccess) slot = -1;
+        }
+    }
+    ~ProfScope() {
+        if (slot >= 0 && hipEventRecord(p->prof_stop[slot], s) == hipSuccess)
+            p->prof_pending.push_back({kind, slot, bytes, flops});
+    }
+};
+
+struct Buffers {
+    // per relation: own sums (key groups) and sigma (parent groups)
+    std::vector<const double *> own;
+    std::vector<int64_t> ld_own;
+    std::vector<const double *> sigma;
+    std::vector<int64_t> ld_sigma;
+};
+
+figaro_status check_inputs(figaro_plan_s *p, const double *const *values, const int64_t *ld) {
+    if (p->analyze_only) return set_error(p, FIGARO_EINVAL, "the plan was built with analyze_only");
+    if (!values || !ld) return set_error(p, FIGARO_EINVAL, "values/ld is NULL");
+    for (int i = 0; i < p->r; ++i) {
+        if (!values[i]) return set_error(p, FIGARO_EINVAL, "values[" + std::to_string(i) + "] is NULL");
+        if (ld[i] < p->rel[i].m)
+            return set_error(p, FIGARO_EINVAL, "ld[" + std::to_string(i) + "] is smaller than the plan rows");
+    }
+    return FIGARO_OK;
+}
+
+// Run the levels of one head/tail task; returns the group sums.
+figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_in, bool fuse, double *r0,
+                       int64_t ld_r0, int32_t *block_of_row, hipStream_t s, const double **group_sums,
+                       int64_t *ld_groups) {
+    const double *cur = in;
+    int64_t ld = ld_in;
+    for (auto &L : T.levels) {
+        HelmertArgs a{};
+        a.in = cur;
+        a.ld_in = ld;
+        a.ncols = T.ncols;
+        a.items = L.items;
+        a.pid = L.d_pid;
+        a.piece_start = L.d_piece_start;
+        a.phi_piece = L.d_phi_piece;
+        a.alpha = L.d_alpha;
+        a.beta = L.d_beta;
+        a.chunk_start = L.d_chunk_start;
+        a.nchunks = L.nchunks;
+        a.pieces_out = L.d_pieces;
+        a.ld_pieces = L.npieces;
+        a.stack = p->d_stack[0];
+        a.ld_stack = p->stack_ld[0];
+        a.stack_row0 = L.stack_row0;
+        a.n_total = p->n;
+        a.inv_colmap = T.d_inv_colmap;
+        a.colmap = T.d_colmap;
+        a.r0 = r0;
+        a.ld_r0 = ld_r0;
+        a.r0_row0 = L.r0_row0;
+        a.block_of_row = block_of_row;
+        a.block_id = T.block_id;
+        a.waves = L.waves;
+        {
+            const int kind = (&L != &T.levels[0]) ? 2 : (L.unit ? 0 : 1);
+            const double bytes = 8.0 * (double)L.items * T.ncols;
+            const double flops = fuse ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
+            ProfScope ps(p, s, kind, bytes, flops);
+            FIGARO_TRY(launch_helmert(a, L.unit, fuse, s));
+        }
+        cur = L.d_pieces;
+        ld = L.npieces;
+    }
+    *group_sums = cur;
+    *ld_groups = ld;
+    return FIGARO_OK;
+}
+
+figaro_status forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse, double *R,
+                      double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, bool stop_before_tsqr = false) {
+    Buffers B;
+    B.own.assign(p->r, nullptr);
+    B.ld_own.assign(p->r, 0);
+    B.sigma.assign(p->r, nullptr);
+    B.ld_sigma.assign(p->r, 0);
+    for (int v : p->post) {
+        RelPlan &Rl = p->rel[v];
+        // heads_and_tails: own key-group sums and the tails of S_v
+        if (Rl.a2.active) {
+            figaro_status st = run_task(p, Rl.a2, values[v], ld[v], fuse, r0, ld_r0, block_of_row, s, &B.own[v],
+                                        &B.ld_own[v]);
+            if (st != FIGARO_OK) return st;
+        } else {
+            B.own[v] = values[v];
+            B.ld_own[v] = ld[v];
+        }
+        const double *items = B.own[v];
+        int64_t ld_items = B.ld_own[v];
+        if (!Rl.children.empty()) {
+            // process_and_join_children
+            JoinArgs j{};
+            j.groups = Rl.G;
+            j.nsub = Rl.nsub;
+            j.s = Rl.d_s;
+            j.ld_s = Rl.G;
+            j.own = B.own[v];
+            j.ld_own = B.ld_own[v];
+            j.own_cols = Rl.ncols;
+            j.own_pos = Rl.own_pos;
+            j.own_mult = Rl.d_own_mult;
+            j.nchildren = (int32_t)Rl.children.size();
+            for (size_t c = 0; c < Rl.children.size(); ++c) {
+                int ch = Rl.children[c];
+                j.sigma[c] = B.sigma[ch];
+                j.ld_sigma[c] = B.ld_sigma[ch];
+                j.child_cols[c] = p->rel[ch].nsub;
+                j.colpos[c] = Rl.d_colpos[c];
+                j.cidx[c] = Rl.d_cidx[c];
+                j.mult[c] = Rl.d_mult[c];
+            }
+            {
+                ProfScope ps(p, s, 3, 8.0 * (double)Rl.G * (Rl.ncols + 2.0 * Rl.nsub), 0.0);
+                FIGARO_TRY(launch_join(j, s));
+            }
+            items = Rl.d_s;
+            ld_items = Rl.G;
+        }
+        if (Rl.parent >= 0) {
+            // project_away_join_attributes (only non-leaves with P < G have tails)
+            if (Rl.a4.active) {
+                figaro_status st = run_task(p, Rl.a4, items, ld_items, fuse, r0, ld_r0, block_of_row, s,
+                                            &B.sigma[v], &B.ld_sigma[v]);
+                if (st != FIGARO_OK) return st;
+            } else {
+                B.sigma[v] = items;
+                B.ld_sigma[v] = ld_items;
+            }
+        } else {
+            RootArgs ra{};
+            ra.groups = Rl.G;
+            ra.n = p->n;
+            ra.s = items;
+            ra.ld_s = ld_items;
+            ra.inv_sqrt_c = Rl.d_inv_sqrt_c;
+            ra.dst = fuse ? p->d_stack[0] : r0;
+            ra.ld_dst = fuse ? p->stack_ld[0] : ld_r0;
+            ra.row0 = fuse ? Rl.root_row0 : Rl.r0_root_row0;
+            ra.block_of_row = fuse ? nullptr : block_of_row;
+            ra.block_id = 3 * v + 2;
+            {
+                ProfScope ps(p, s, 4, 16.0 * (double)Rl.G * p->n, 0.0);
+                FIGARO_TRY(launch_root(ra, !fuse, s));
+            }
+        }
+    }
+    if (!fuse || stop_before_tsqr) return FIGARO_OK;
+    // post-processing TSQR over the stack
+    int cur = 0;
+    for (size_t d = 0; d < p->dense.size(); ++d) {
+        const DenseLevel &D = p->dense[d];
+        DenseArgs a{};
+        a.in = p->d_stack[cur];
+        a.ld_in = p->stack_ld[cur];
+        a.rows = D.rows;
+        a.n = p->n;
+        a.out = p->d_stack[1 - cur];
+        a.ld_out = p->stack_ld[1 - cur];
+        a.waves = D.waves;
+        a.tiles_per_wave = D.tiles_per_wave;
+        a.final_r = R;
+        {
+            ProfScope ps(p, s, 5, 8.0 * (double)D.rows * p->n, 2.0 * (double)D.rows * p->n * p->n);
+            FIGARO_TRY(launch_dense(a, s));
+        }
+        cur = 1 - cur;
+    }
+    return FIGARO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+figaro_status figaro_r(figaro_plan_t p, const double *const *values, const int64_t *ld, double *R,
+                       hipStream_t stream) {
+    if (!p) return set_error(nullptr, FIGARO_EINVAL, "plan is NULL");
+    if (!R) return set_error(p, FIGARO_EINVAL, "R is NULL");
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    return forward(p, values, ld, true, R, nullptr, 0, nullptr, stream);
+}
+
+int64_t figaro_r0_rows(figaro_plan_t p) { return p ? p->r0_rows : -1; }
+
+figaro_status figaro_r0(figaro_plan_t p, const double *const *values, const int64_t *ld, double *R0,
+                        int64_t ld_r0, int32_t *block_of_row, hipStream_t stream) {
+    if (!p) return set_error(nullptr, FIGARO_EINVAL, "plan is NULL");
+    if (!R0 || ld_r0 < p->r0_rows) return set_error(p, FIGARO_EINVAL, "R0 is NULL or ld_r0 too small");
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    hipError_t e = launch_fill(R0, (int64_t)p->n * ld_r0, 0.0, stream);
+    if (e != hipSuccess) return set_error(p, FIGARO_EHIP, hipGetErrorString(e));
+    if (block_of_row) {
+        e = launch_fill_i32(block_of_row, p->r0_rows, -1, stream);
+        if (e != hipSuccess) return set_error(p, FIGARO_EHIP, hipGetErrorString(e));
+    }
+    return forward(p, values, ld, false, nullptr, R0, ld_r0, block_of_row, stream);
+}
+
+figaro_status figaro_permute_values(figaro_plan_t p, int32_t rel, const double *src, int64_t ld_src, double *dst,
+                                    int64_t ld_dst, hipStream_t stream) {
+    if (!p || rel < 0 || rel >= p->r || !src || !dst || p->analyze_only)
+        return set_error(p, FIGARO_EINVAL, "bad argument");
+    const RelPlan &R = p->rel[rel];
+    if (ld_src < R.m_in || ld_dst < R.m) return set_error(p, FIGARO_EINVAL, "leading dimension too small");
+    hipError_t e = launch_permute(src, ld_src, dst, ld_dst, R.d_perm, R.m, R.ncols, false, R.m_in, stream);
+    return e == hipSuccess ? FIGARO_OK : set_error(p, FIGARO_EHIP, hipGetErrorString(e));
+}
+
+figaro_status figaro_unpermute_values(figaro_plan_t p, int32_t rel, const double *src, int64_t ld_src, double *dst,
+                                      int64_t ld_dst, hipStream_t stream) {
+    if (!p || rel < 0 || rel >= p->r || !src || !dst || p->analyze_only)
+        return set_error(p, FIGARO_EINVAL, "bad argument");
+    const RelPlan &R = p->rel[rel];
+    if (ld_src < R.m || ld_dst < R.m_in) return set_error(p, FIGARO_EINVAL, "leading dimension too small");
+    hipError_t e = launch_permute(src, ld_src, dst, ld_dst, R.d_perm, R.m, R.ncols, true, R.m_in, stream);
+    return e == hipSuccess ? FIGARO_OK : set_error(p, FIGARO_EHIP, hipGetErrorString(e));
+}
+
+int64_t figaro_debug_stack_rows(figaro_plan_t p) { return p ? p->stack_rows : -1; }
+
+figaro_status figaro_debug_stack(figaro_plan_t p, const double *const *values, const int64_t *ld, double *host_out,
+                                 hipStream_t stream) {
+    if (!p || !host_out) return set_error(p, FIGARO_EINVAL, "bad argument");
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    st = forward(p, values, ld, true, nullptr, nullptr, 0, nullptr, stream, true);
+    if (st != FIGARO_OK) return st;
+    if (hipStreamSynchronize(stream) != hipSuccess) return set_error(p, FIGARO_EHIP, "sync failed");
+    for (int c = 0; c < p->n; ++c)
+        if (hipMemcpy(host_out + (size_t)c * p->stack_rows, p->d_stack[0] + (size_t)c * p->stack_ld[0],
+                      sizeof(double) * (size_t)p->stack_rows, hipMemcpyDeviceToHost) != hipSuccess)
+            return set_error(p, FIGARO_EHIP, "copy failed");
+    return FIGARO_OK;
+}
+
+figaro_status figaro_profile_enable(figaro_plan_t p, int32_t capacity) {
+    if (!p || capacity < 0) return set_error(p, FIGARO_EINVAL, "bad argument");
+    for (auto e : p->prof_start) (void)hipEventDestroy(e);
+    for (auto e : p->prof_stop) (void)hipEventDestroy(e);
+    p->prof_start.clear();
+    p->prof_stop.clear();
+    p->prof_pending.clear();
+    p->prof_next = 0;
+    for (int32_t q = 0; q < capacity; ++q) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return set_error(p, FIGARO_EHIP, "hipEventCreate failed");
+        if (hipEventCreate(&b) != hipSuccess) return set_error(p, FIGARO_EHIP, "hipEventCreate failed");
+        p->prof_start.push_back(a);
+        p->prof_stop.push_back(b);
+    }
+    return FIGARO_OK;
+}
+
+static figaro_status prof_drain(figaro_plan_s *p) {
+    for (const auto &q : p->prof_pending) {
+        if (hipEventSynchronize(p->prof_stop[q.slot]) != hipSuccess)
+            return set_error(p, FIGARO_EHIP, "hipEventSynchronize failed");
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p->prof_start[q.slot], p->prof_stop[q.slot]) != hipSuccess)
+            return set_error(p, FIGARO_EHIP, "hipEventElapsedTime failed");
+        p->prof_ms[q.kind] += ms;
+        p->prof_launches[q.kind] += 1;
+        p->prof_bytes[q.kind] += q.bytes;
+        p->prof_flops[q.kind] += q.flops;
+    }
+    p->prof_pending.clear();
+    p->prof_next = 0;
+    return FIGARO_OK;
+}
+
+figaro_status figaro_profile_read(figaro_plan_t p, int32_t kind, double *ms, int64_t *launches, double *bytes,
+                                  double *flops) {
+    if (!p || kind < 0 || kind >= kProfClasses) return set_error(p, FIGARO_EINVAL, "bad argument");
+    figaro_status st = prof_drain(p);
+    if (st != FIGARO_OK) return st;
+    if (ms) *ms = p->prof_ms[kind];
+    if (launches) *launches = p->prof_launches[kind];
+    if (bytes) *bytes = p->prof_bytes[kind];
+    if (flops) *flops = p->prof_flops[kind];
+    return FIGARO_OK;
+}
+
+figaro_status figaro_profile_reset(figaro_plan_t p) {
+    if (!p) return set_error(p, FIGARO_EINVAL, "bad argument");
+    figaro_status st = prof_drain(p);
+    for (int k = 0; k < kProfClasses; ++k) {
+        p->prof_ms[k] = 0;
+        p->prof_launches[k] = 0;
+        p->prof_bytes[k] = 0;
+        p->prof_flops[k] = 0;
+    }
+    return st;
+}
+
+}  // extern "C"
