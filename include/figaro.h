@@ -95,6 +95,10 @@ typedef struct {
     int32_t waves_per_task;     /* upper bound on waves of one head/tail
                                    launch, 0 = default */
     int32_t keys_on_host;       /* 1: key_cols are host pointers */
+    int32_t variant;            /* form of the register-tile Householder QR:
+                                   0 fully unrolled (triangular work), 1
+                                   compact runtime column loop (smaller code,
+                                   twice the arithmetic) */
     int32_t analyze_only;       /* 1: stop after the count queries; the plan
                                    then answers the info and count queries
                                    only, holds no device memory, and the
@@ -167,6 +171,31 @@ figaro_status figaro_unpermute_values(figaro_plan_t plan, int32_t rel, const dou
  */
 figaro_status figaro_r(figaro_plan_t plan, const double *const *values, const int64_t *ld,
                        double *R, hipStream_t stream);
+
+/*
+ * Backward: gradients of a scalar loss with respect to every relation's values,
+ * given dR = dLoss/dR.  Only the upper triangle of dR is used (the strictly
+ * lower part of R is structurally zero).  The paper has no backward pass; this
+ * is the adjoint of the forward computation: with
+ *   K = R^{-1} copyltu(R triu(dR)^T) R^{-T},  copyltu(M) = tril(M) + tril(M,-1)^T,
+ * the gradient of the join matrix is A K (the adjoint of the R factor of a QR
+ * decomposition), and the library pushes the gradients of the R0 rows (R0 K on
+ * each row's non-zero columns) back through the head/tail recurrences, the
+ * join of the children's heads and the root heads, recomputing the forward
+ * intermediates instead of storing them.
+ *   values, ld : as for figaro_r (plan order)
+ *   R          : the R that figaro_r returned for these values (n x n)
+ *   dR         : device n x n column-major
+ *   dvalues[i] : device output, plan order, leading dim ld_dvalues[i] >= rows;
+ *                every kept row is written
+ * Enqueued on `stream`; no allocation, no host synchronisation.  A zero on
+ * the diagonal of R makes the gradient non-finite; figaro_backward_status()
+ * synchronises `stream` and reports FIGARO_ESINGULAR in that case.
+ */
+figaro_status figaro_r_backward(figaro_plan_t plan, const double *const *values, const int64_t *ld,
+                                const double *R, const double *dR, double *const *dvalues,
+                                const int64_t *ld_dvalues, hipStream_t stream);
+figaro_status figaro_backward_status(figaro_plan_t plan, hipStream_t stream);
 
 /*
  * The intermediate matrix R0 of Theorem 6 (heads and tails before the

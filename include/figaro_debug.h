@@ -19,6 +19,10 @@ int64_t figaro_debug_stack_rows(figaro_plan_t plan);
 figaro_status figaro_debug_stack(figaro_plan_t plan, const double *const *values, const int64_t *ld,
                                  double *host_out, hipStream_t stream);
 
+/* Layout of the stack: up to max_regions triples (block id, first row, rows)
+ * written to regions_host; returns the number of regions. */
+int32_t figaro_debug_stack_layout(figaro_plan_t plan, int64_t *regions_host, int32_t max_regions);
+
 #ifdef __cplusplus
 }
 #endif

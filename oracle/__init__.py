@@ -74,6 +74,9 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.or_join.restype = ctypes.c_int64
         lib.or_join.argtypes = [ctypes.c_int, ctypes.POINTER(_ORel), dp, ctypes.c_int64, ctypes.c_int64]
+        lib.or_join_idx.restype = ctypes.c_int64
+        lib.or_join_idx.argtypes = [ctypes.c_int, ctypes.POINTER(_ORel), ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_int64, ctypes.c_int64]
         lib.or_householder_r.restype = ctypes.c_int
         lib.or_householder_r.argtypes = [ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64, dp]
         lib.or_givens_r.restype = ctypes.c_int
@@ -140,6 +143,20 @@ def join(inst, max_rows: int | None = None) -> np.ndarray:
     if got < 0:
         raise ValueError("join enumeration failed")
     return np.asfortranarray(A[:, :got].T)
+
+
+def join_indices(inst) -> np.ndarray:
+    """The join as tuple indices: (r, rows) array, entry [i, row] is the tuple
+    of relation i in that join row (same row order as join())."""
+    lib = _load()
+    rows = join_size(inst)
+    arr, keep = _orels(inst)
+    idx = np.zeros((inst.r, max(rows, 1)), dtype=np.int64)
+    got = lib.or_join_idx(inst.r, arr, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), max(rows, 1),
+                          max(rows, 1))
+    if got < 0:
+        raise ValueError("join enumeration failed")
+    return idx[:, :got]
 
 
 def householder_r(A: np.ndarray) -> Tuple[np.ndarray, int]:
@@ -513,3 +530,43 @@ def figaro_alg3(inst):
 def stack_blocks(blocks) -> np.ndarray:
     rows = [b["rows"] for b in blocks if b["rows"].shape[0] > 0]
     return np.concatenate(rows, axis=0) if rows else np.zeros((0, 0))
+
+
+# ---------------------------------------------------------------------------
+# Gradients (the paper has no backward pass; these are plain references)
+# ---------------------------------------------------------------------------
+
+def grad_autograd(inst, loss_fn):
+    """Gradients of loss_fn(R) with respect to every relation's values by
+    autograd (PyTorch, CPU, FP64) through the QR of the materialised join:
+    A = [values_i[:, idx_i]^T], R = qr(A).R with a non-negative diagonal.
+    Returns (list of (n_i, m_i) arrays, R)."""
+    import torch
+    idx = join_indices(inst)
+    vs = [torch.tensor(np.ascontiguousarray(rel.values), dtype=torch.float64, requires_grad=True)
+          for rel in inst.rels]
+    A = torch.cat([vs[i][:, torch.as_tensor(idx[i])].T for i in range(inst.r)], dim=1)
+    R = torch.linalg.qr(A, mode="reduced")[1]
+    d = torch.diagonal(R)
+    R = torch.where(d < 0, -1.0, 1.0)[:, None] * R
+    L = loss_fn(R)
+    L.backward()
+    return [v.grad.numpy().copy() for v in vs], R.detach().numpy()
+
+
+def grad_logdet_closed_form(inst):
+    """d/dvalues of sum_i log R_ii: since sum log R_ii = (1/2) log det(A^T A),
+    dA = A (A^T A)^{-1}; the gradient of a tuple's values is the sum of dA
+    over the join rows that contain the tuple (the join's adjoint)."""
+    A = join(inst)
+    idx = join_indices(inst)
+    G = A.T @ A
+    dA = A @ np.linalg.inv(G)
+    out = []
+    c0 = 0
+    for i, rel in enumerate(inst.rels):
+        g = np.zeros_like(rel.values)
+        np.add.at(g.T, idx[i], dA[:, c0:c0 + rel.ncols])
+        out.append(g)
+        c0 += rel.ncols
+    return out

@@ -138,6 +138,7 @@ typedef struct {
     int64_t *cur;          /* current row per relation */
     int64_t *col_off;      /* global column offset per relation */
     double *A;             /* output, column-major, may be NULL (count only) */
+    int64_t *idx;          /* output tuple indices [r][lda], may be NULL */
     int64_t lda;
     int64_t rows;          /* rows emitted so far */
     int64_t max_rows;
@@ -147,6 +148,10 @@ typedef struct {
 static void join_rec(join_ctx *c, int depth) {
     if (c->overflow) return;
     if (depth == c->r) {
+        if (c->idx) {
+            if (c->rows >= c->max_rows) { c->overflow = 1; return; }
+            for (int i = 0; i < c->r; ++i) c->idx[(int64_t)i * c->lda + c->rows] = c->cur[i];
+        }
         if (c->A) {
             if (c->rows >= c->max_rows) { c->overflow = 1; return; }
             for (int i = 0; i < c->r; ++i) {
@@ -218,6 +223,40 @@ int64_t or_join(int r, const orel *rels, double *A, int64_t lda, int64_t max_row
         if (rindex_build(&c.ix[i], &rels[i], pc, ns) != 0) goto done;
     }
     c.A = A;
+    c.lda = lda;
+    c.max_rows = max_rows;
+    join_rec(&c, 0);
+    result = c.overflow ? -2 : c.rows;
+done:
+    for (int i = 0; i < r; ++i) free(c.ix[i].order);
+    free(c.order); free(c.ix); free(c.ppos); free(c.npp); free(c.cur); free(c.col_off);
+    return result;
+}
+
+/* The join as tuple indices: idx[i*lda + row] is the tuple of relation i in
+ * join row `row` (same row order as or_join). */
+int64_t or_join_idx(int r, const orel *rels, int64_t *idx, int64_t lda, int64_t max_rows) {
+    join_ctx c;
+    memset(&c, 0, sizeof c);
+    c.r = r;
+    c.rels = rels;
+    c.order = (int *)malloc(sizeof(int) * (size_t)r);
+    c.ix = (row_index *)calloc((size_t)r, sizeof(row_index));
+    c.ppos = malloc(sizeof(int[64]) * (size_t)r);
+    c.npp = (int *)calloc((size_t)r, sizeof(int));
+    c.cur = (int64_t *)calloc((size_t)r, sizeof(int64_t));
+    c.col_off = (int64_t *)calloc((size_t)r, sizeof(int64_t));
+    int64_t result = -1;
+    if (preorder(r, rels, c.order) != 0) goto done;
+    for (int i = 0; i < r; ++i) {
+        if (rels[i].parent < 0) continue;
+        int pc[64], pp[64];
+        int ns = shared_attrs(&rels[i], &rels[rels[i].parent], pc, pp);
+        c.npp[i] = ns;
+        for (int a = 0; a < ns; ++a) c.ppos[i][a] = pp[a];
+        if (rindex_build(&c.ix[i], &rels[i], pc, ns) != 0) goto done;
+    }
+    c.idx = idx;
     c.lda = lda;
     c.max_rows = max_rows;
     join_rec(&c, 0);

@@ -38,7 +38,8 @@ class RelationDesc(ctypes.Structure):
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("tile_items", ctypes.c_int32), ("waves_per_task", ctypes.c_int32),
-                ("keys_on_host", ctypes.c_int32), ("analyze_only", ctypes.c_int32)]
+                ("keys_on_host", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("analyze_only", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,9 +84,11 @@ def lib():
         "figaro_profile_reset": (i32, [vp]),
         "figaro_debug_stack_rows": (i64, [vp]),
         "figaro_debug_stack": (i32, [vp, pp, pi64, vp, vp]),
+        "figaro_debug_stack_layout": (i32, [vp, pi64, i32]),
     }
     optional = {
-        "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, vp]),
+        "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, pi64, vp]),
+        "figaro_backward_status": (i32, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -125,7 +128,7 @@ class Plan:
     and parent (int, -1 for the root)."""
 
     def __init__(self, relations: Sequence, *, tile_items: int = 0, waves_per_task: int = 0,
-                 stream=None, analyze_only: bool = False):
+                 stream=None, analyze_only: bool = False, variant: int = 0):
         L = lib()
         if analyze_only:
             self._init_host(relations, tile_items, waves_per_task)
@@ -151,7 +154,7 @@ class Plan:
             descs[i].parent = int(rel.parent)
             if hasattr(rel, "rows_override"):
                 descs[i].rows = int(rel.rows_override)
-        opts = PlanOptions(tile_items, waves_per_task, 0, 0)
+        opts = PlanOptions(tile_items, waves_per_task, 0, variant, 0)
         st = L.figaro_plan_create(ctypes.byref(self._handle), r, descs, ctypes.byref(opts),
                                   _stream_handle(stream))
         if st != FIGARO_OK:
@@ -183,7 +186,7 @@ class Plan:
             descs[i].key_dtype = 8 if keys.dtype == np.int64 else 4
             descs[i].num_cols = int(rel.values.shape[0]) if hasattr(rel, "values") else int(rel.ncols)
             descs[i].parent = int(rel.parent)
-        opts = PlanOptions(tile_items, waves_per_task, 1, 1)
+        opts = PlanOptions(tile_items, waves_per_task, 1, 0, 1)
         st = L.figaro_plan_create(ctypes.byref(self._handle), r, descs, ctypes.byref(opts), None)
         if st != FIGARO_OK:
             msg = L.figaro_last_error(None)
@@ -283,6 +286,26 @@ class Plan:
                               _stream_handle(stream)), self._handle)
         return out.T
 
+    def r_backward(self, values: List, R, dR, stream=None):
+        """Gradients of a loss with respect to the values (plan order), given
+        R from r_factor() and dR = dLoss/dR (only its upper triangle is used)."""
+        import torch
+        ptrs, lds = self._value_args(values)
+        Rc = R.detach().T.contiguous()     # column-major n x n
+        dRc = dR.detach().to(torch.float64).T.contiguous()
+        outs = [torch.empty((self.ncols[i], max(self.rows(i), 1)), dtype=torch.float64, device=values[0].device)
+                for i in range(self.r)]
+        optr = (ctypes.c_void_p * self.r)(*[o.data_ptr() for o in outs])
+        olds = (ctypes.c_int64 * self.r)(*[max(o.stride(0), self.rows(i)) for i, o in enumerate(outs)])
+        _check(lib().figaro_r_backward(self._handle, ptrs, lds, ctypes.c_void_p(Rc.data_ptr()),
+                                       ctypes.c_void_p(dRc.data_ptr()), optr, olds, _stream_handle(stream)),
+               self._handle)
+        return [o[:, :self.rows(i)] for i, o in enumerate(outs)]
+
+    def backward_status(self, stream=None) -> str:
+        st = lib().figaro_backward_status(self._handle, _stream_handle(stream))
+        return STATUS_NAMES.get(st, str(st))
+
     def r0(self, values: List, stream=None):
         """The intermediate R0 (rows x n) and the block id of every row."""
         import torch
@@ -302,6 +325,11 @@ class Plan:
         _check(lib().figaro_debug_stack(self._handle, ptrs, lds, ctypes.c_void_p(out.ctypes.data),
                                         _stream_handle(stream)), self._handle)
         return out[:, :rows].T
+
+    def debug_stack_layout(self):
+        out = np.zeros(3 * 256, dtype=np.int64)
+        k = lib().figaro_debug_stack_layout(self._handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 256)
+        return out[:3 * k].reshape(k, 3)
 
     # -- profiling ------------------------------------------------------------
     PROFILE_CLASSES = {0: "heads_tails", 1: "project_away", 2: "upper_levels", 3: "join",
@@ -333,6 +361,40 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _make_autograd():
+    import torch
+
+    class FigaroR(torch.autograd.Function):
+        """R of the join as a differentiable function of the relation values
+        (plan order).  Backward runs the library's adjoint."""
+
+        @staticmethod
+        def forward(ctx, plan, *values):
+            R = plan.r_factor(list(values)).clone()
+            ctx.plan = plan
+            ctx.save_for_backward(R, *values)
+            return R
+
+        @staticmethod
+        def backward(ctx, dR):
+            R, *values = ctx.saved_tensors
+            grads = ctx.plan.r_backward(list(values), R, dR.contiguous())
+            return (None, *grads)
+
+    return FigaroR
+
+
+_FigaroR = None
+
+
+def figaro_r(plan, *values):
+    """Differentiable R (torch.autograd): figaro_r(plan, v_0, ..., v_{r-1})."""
+    global _FigaroR
+    if _FigaroR is None:
+        _FigaroR = _make_autograd()
+    return _FigaroR.apply(plan, *values)
 
 
 class _RelView:

@@ -51,8 +51,8 @@ struct HelmertArgs {
     int64_t ld_stack;
     int64_t stack_row0;
     int32_t n_total;
-    const int32_t *inv_colmap;   // [n_total]: local column of a global column, or -1
-    const int32_t *colmap;       // [ncols]: global column of a local column
+    uint64_t other_cols;         // bit g set: global column g is not a column of this block
+    int8_t colmap[kMaxCols];     // global column of every local column
     // R0 output (materialisation for inspection)
     double *r0;
     int64_t ld_r0;
@@ -62,9 +62,10 @@ struct HelmertArgs {
     int32_t waves;
 };
 
-// Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); each wave writes its
-// R (n rows) to `out` rows wave*n, or the final R (sign-normalised) to
-// `final_r` when waves == 1.
+// Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
+// `waves` workgroups, 4 waves each, tiles_per_wave tiles per wave) writes its
+// R (n rows) to `out` rows b*n, or the final R (sign-normalised) to `final_r`
+// when there is a single workgroup.
 struct DenseArgs {
     const double *in;
     int64_t ld_in;
@@ -75,6 +76,31 @@ struct DenseArgs {
     int32_t waves;
     int64_t tiles_per_wave;
     double *final_r;
+};
+
+// Backward of one head/tail level: recompute the tails of every chunk, take
+// dT = T K_blk (K_blk: K restricted to the block's columns), and write the
+// gradient of every item:  ds_t = alpha_t dT_t - sum_{u > t in its piece}
+// beta_u dT_u + dsigma[piece of t].
+struct HelmertBwdArgs {
+    const double *in;
+    int64_t ld_in;
+    int32_t ncols;
+    const int32_t *pid;
+    const int64_t *piece_start;
+    const double *phi_piece;
+    const double *alpha;
+    const double *beta;
+    const int64_t *chunk_start;
+    int64_t nchunks;
+    const double *K;             // n_total x n_total, column-major
+    int32_t n_total;
+    int8_t colmap[64];
+    const double *gpieces;       // gradient of the piece sums, [ncols][ld_gp]
+    int64_t ld_gp;
+    double *gout;                // gradient of the items, [ncols][ld_gout]
+    int64_t ld_gout;
+    int32_t waves;
 };
 
 constexpr int kMaxChildren = 16;
@@ -115,20 +141,64 @@ struct RootArgs {
     int32_t block_id;
 };
 
+// Backward of process_and_join_children: own-column gradient scaled by
+// own_mult, and for every child group q the sum over the parent key groups
+// that join it (plan-time inverse index, deterministic order).
+struct JoinBwdArgs {
+    int64_t groups;
+    const double *ds;            // [nsub][ld_ds]
+    int64_t ld_ds;
+    double *dOwn;                // [own_cols][ld_own]
+    int64_t ld_own;
+    int32_t own_cols;
+    int32_t own_pos;
+    const double *own_mult;
+    int32_t nchildren;
+    double *dsigma[kMaxChildren];
+    int64_t ld_dsigma[kMaxChildren];
+    int64_t child_groups[kMaxChildren];
+    int32_t child_cols[kMaxChildren];
+    const int32_t *colpos[kMaxChildren];
+    const int64_t *inv_off[kMaxChildren];   // [child groups + 1]
+    const int32_t *inv_idx[kMaxChildren];   // parent key groups sorted by child group
+    const double *mult[kMaxChildren];
+};
+
+// Backward of the root heads: row_g = s_g / sqrt(c_g), d row_g = row_g K,
+// ds_g = d row_g / sqrt(c_g).
+struct RootBwdArgs {
+    int64_t groups;
+    int32_t n;
+    const double *s;
+    int64_t ld_s;
+    const double *inv_sqrt_c;
+    const double *K;
+    double *ds;
+    int64_t ld_ds;
+};
+
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
-hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s);
-hipError_t launch_dense(const DenseArgs &a, hipStream_t s);
+hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s);
+hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s);
 hipError_t launch_join(const JoinArgs &a, hipStream_t s);
 hipError_t launch_root(const RootArgs &a, bool to_r0, hipStream_t s);
 hipError_t launch_permute(const double *src, int64_t ld_src, double *dst, int64_t ld_dst,
                           const int64_t *perm, int64_t rows, int32_t ncols, bool inverse,
                           int64_t total_rows, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
+hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, int32_t *status,
+                             hipStream_t s);
+hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s);
+hipError_t launch_join_bwd(const JoinBwdArgs &a, hipStream_t s);
+hipError_t launch_root_bwd(const RootBwdArgs &a, hipStream_t s);
+hipError_t launch_copy_cols(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
+                            int32_t ncols, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
-int tile_items_for(int ncols);        // items per chunk of the register-tile kernel
+int tile_items_for(int ncols, int variant);   // items per chunk of the register-tile kernel
 int dense_tile_rows_for(int ncols);   // rows per tile of the dense kernel
+int waves_per_block();                // waves per workgroup of the QR kernels
 
 // ---------------------------------------------------------------------------
 // Plan
@@ -147,11 +217,13 @@ struct Level {
     double *d_phi_piece = nullptr;
     double *d_alpha = nullptr, *d_beta = nullptr;
     double *d_pieces = nullptr;   // [ncols][npieces]
+    double *d_gpieces = nullptr;  // gradient of the piece sums, [ncols][npieces]
 };
 
 // heads_and_tails (A2) or project_away_join_attributes (A4) of one relation.
 struct Task {
     bool active = false;
+    int32_t variant = 0;          // tile shape of the head/tail kernel
     int32_t ncols = 0;
     int32_t block_id = 0;
     std::vector<int32_t> cols;    // global columns, ascending
@@ -191,6 +263,9 @@ struct RelPlan {
     std::vector<double *> d_mult;
     std::vector<int32_t *> d_colpos;
     double *d_s = nullptr;           // [nsub][G]
+    double *d_gs = nullptr;          // gradient of s, [nsub][G]
+    std::vector<int64_t *> d_inv_off;   // per child: [P_child+1]
+    std::vector<int32_t *> d_inv_idx;   // per child: [G]
     // projection onto X_p
     Task a4;
     // root
@@ -226,12 +301,15 @@ struct figaro_plan_s {
     int32_t tile_items = 0;
     int32_t waves_cap = 0;
     bool analyze_only = false;
+    int32_t variant = 0;
     // stack for the post-processing TSQR
     int64_t stack_rows = 0;
     double *d_stack[2] = {nullptr, nullptr};
     int64_t stack_ld[2] = {0, 0};
     std::vector<figaro::DenseLevel> dense;
     int64_t r0_rows = 0;
+    double *d_K = nullptr;           // n x n, backward
+    int32_t *d_status = nullptr;     // device status word of the backward pass
     int64_t workspace_bytes = 0;
     std::vector<void *> allocations;
     std::string last_error;

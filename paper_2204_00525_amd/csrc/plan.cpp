@@ -218,7 +218,8 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
             if (dev_upload(p, &L.d_alpha, al) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
             if (dev_upload(p, &L.d_beta, be) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         }
-        if (dev_alloc(p, (void **)&L.d_pieces, sizeof(double) * (size_t)T.ncols * (size_t)L.npieces) != hipSuccess)
+        if (dev_alloc(p, (void **)&L.d_pieces, sizeof(double) * (size_t)T.ncols * (size_t)L.npieces) != hipSuccess ||
+            dev_alloc(p, (void **)&L.d_gpieces, sizeof(double) * (size_t)T.ncols * (size_t)L.npieces) != hipSuccess)
             return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         L.waves = (int32_t)std::min<int64_t>(L.nchunks, p->waves_cap);
         if (L.waves < 1) L.waves = 1;
@@ -252,9 +253,11 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     p->r = r;
     p->rel.resize(r);
     p->tile_items = opts ? opts->tile_items : 0;
-    p->waves_cap = (opts && opts->waves_per_task > 0) ? opts->waves_per_task : 2048;
+    p->waves_cap = (opts && opts->waves_per_task > 0) ? opts->waves_per_task : 1024;
     const bool keys_on_host = opts && opts->keys_on_host;
     p->analyze_only = opts && opts->analyze_only;
+    p->variant = opts ? opts->variant : 0;
+    if (p->variant < 0 || p->variant > 1) return set_error(p, FIGARO_EINVAL, "variant must be 0 or 1");
     if (p->tile_items < 0) return set_error(p, FIGARO_EINVAL, "tile_items must be >= 0");
     // ---- argument checks
     int roots = 0;
@@ -572,7 +575,9 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     }
     for (int v : p->post) {
         auto &R = p->rel[v];
-        const int tile_a2 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.ncols)) : tile_items_for(R.ncols);
+        R.a2.variant = p->variant;
+        const int tile_a2 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.ncols, p->variant))
+                                              : tile_items_for(R.ncols, p->variant);
         // heads_and_tails of S_v
         if (!R.singleton) {
             R.a2.active = true;
@@ -618,8 +623,25 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             }
             if (R.children.size() > (size_t)kMaxChildren)
                 return set_error(p, FIGARO_EUNSUPPORTED, "more than 16 children of one relation");
-            if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess)
+            if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess ||
+                dev_alloc(p, (void **)&R.d_gs, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess)
                 return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            // inverse of the child index: parent key groups grouped by child group
+            for (size_t c = 0; c < R.children.size(); ++c) {
+                const int64_t Pc = p->rel[R.children[c]].P;
+                std::vector<int64_t> off(Pc + 1, 0);
+                for (int64_t g = 0; g < R.G; ++g) off[cidx[v][c][g] + 1]++;
+                for (int64_t q = 0; q < Pc; ++q) off[q + 1] += off[q];
+                std::vector<int32_t> idx(R.G);
+                std::vector<int64_t> pos(off.begin(), off.end() - 1);
+                for (int64_t g = 0; g < R.G; ++g) idx[pos[cidx[v][c][g]]++] = (int32_t)g;
+                int64_t *doff;
+                int32_t *didx;
+                if (dev_upload(p, &doff, off) != hipSuccess || dev_upload(p, &didx, idx) != hipSuccess)
+                    return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                R.d_inv_off.push_back(doff);
+                R.d_inv_idx.push_back(didx);
+            }
             if (R.parent >= 0 && R.P < R.G) {
                 R.a4.active = true;
                 R.a4.ncols = R.nsub;
@@ -627,7 +649,9 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
                 R.a4.cols = R.sub_cols;
                 std::vector<double> phi(R.P);
                 for (int64_t q = 0; q < R.P; ++q) phi[q] = std::sqrt((double)R.phi_up[q]);
-                const int tile_a4 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.nsub)) : tile_items_for(R.nsub);
+                R.a4.variant = p->variant;
+                const int tile_a4 = p->tile_items > 0 ? std::min(p->tile_items, tile_items_for(R.nsub, p->variant))
+                                                      : tile_items_for(R.nsub, p->variant);
                 figaro_status st = build_task(p, R.a4, R.G, R.par_off, R.theta, phi, tile_a4);
                 if (st != FIGARO_OK) return st;
                 if ((st = finish_task(p, R.a4, n)) != FIGARO_OK) return st;
@@ -647,7 +671,12 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             if (!T->active) continue;
             for (auto &L : T->levels) {
                 L.stack_row0 = srow;
-                srow += (int64_t)L.waves * T->ncols;
+                // the first level folds its tails into one R per workgroup;
+                // the upper levels hold few rows and append their tails as is
+                if (&L == &T->levels[0])
+                    srow += (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols;
+                else
+                    srow += L.items;
                 L.r0_row0 = r0row;
                 r0row += L.items;
             }
@@ -661,25 +690,30 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     }
     p->stack_rows = srow;
     p->r0_rows = r0row;
-    // dense TSQR levels over the stack
-    const int dt = dense_tile_rows_for(n);
+    // dense TSQR levels over the stack: a workgroup (waves_per_block waves)
+    // folds waves_per_block * tiles_per_wave tiles into one R of n rows
+    const int64_t dt = dense_tile_rows_for(n);
+    const int64_t wpb = waves_per_block();
     int64_t rows = srow;
     int64_t maxnext = 0;
     while (true) {
         DenseLevel D;
         D.rows = rows;
-        if (rows <= 4 * (int64_t)dt) {
+        if (rows <= 4 * wpb * dt) {
             D.waves = 1;
-            D.tiles_per_wave = std::max<int64_t>(1, (rows + dt - 1) / dt);
+            D.tiles_per_wave = std::max<int64_t>(1, (rows + wpb * dt - 1) / (wpb * dt));
             p->dense.push_back(D);
             break;
         }
         D.tiles_per_wave = 1;
-        D.waves = (int32_t)((rows + dt - 1) / dt);
+        D.waves = (int32_t)((rows + wpb * dt - 1) / (wpb * dt));
         p->dense.push_back(D);
         rows = (int64_t)D.waves * n;
         maxnext = std::max(maxnext, rows);
     }
+    if (dev_alloc(p, (void **)&p->d_K, sizeof(double) * (size_t)n * (size_t)n) != hipSuccess ||
+        dev_alloc(p, (void **)&p->d_status, sizeof(int32_t) * 4) != hipSuccess)
+        return set_error(p, FIGARO_ENOMEM, "hipMalloc");
     p->stack_ld[0] = std::max<int64_t>(srow, 1);
     p->stack_ld[1] = std::max<int64_t>(maxnext, 1);
     if (dev_alloc(p, (void **)&p->d_stack[0], sizeof(double) * (size_t)n * (size_t)p->stack_ld[0]) != hipSuccess ||

@@ -85,20 +85,27 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
         a.ld_stack = p->stack_ld[0];
         a.stack_row0 = L.stack_row0;
         a.n_total = p->n;
-        a.inv_colmap = T.d_inv_colmap;
-        a.colmap = T.d_colmap;
-        a.r0 = r0;
-        a.ld_r0 = ld_r0;
-        a.r0_row0 = L.r0_row0;
-        a.block_of_row = block_of_row;
+        a.other_cols = ~0ull >> (64 - p->n);
+        for (int c = 0; c < T.ncols; ++c) {
+            a.colmap[c] = (int8_t)T.cols[c];
+            a.other_cols &= ~(1ull << T.cols[c]);
+        }
+        // upper levels of the fused pass write their tail rows into the stack
+        const bool fold = fuse && (&L == &T.levels[0]);
+        const bool to_stack = fuse && !fold;
+        a.r0 = to_stack ? p->d_stack[0] : r0;
+        a.ld_r0 = to_stack ? p->stack_ld[0] : ld_r0;
+        a.r0_row0 = to_stack ? L.stack_row0 : L.r0_row0;
+        if (fold && !r0) a.r0 = nullptr;
+        a.block_of_row = to_stack ? nullptr : block_of_row;
         a.block_id = T.block_id;
         a.waves = L.waves;
         {
             const int kind = (&L != &T.levels[0]) ? 2 : (L.unit ? 0 : 1);
             const double bytes = 8.0 * (double)L.items * T.ncols;
-            const double flops = fuse ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
+            const double flops = fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
             ProfScope ps(p, s, kind, bytes, flops);
-            FIGARO_TRY(launch_helmert(a, L.unit, fuse, s));
+            FIGARO_TRY(launch_helmert(a, L.unit, fold, T.variant, s));
         }
         cur = L.d_pieces;
         ld = L.npieces;
@@ -109,7 +116,9 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
 }
 
 figaro_status forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse, double *R,
-                      double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, bool stop_before_tsqr = false) {
+                      double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, bool stop_before_tsqr = false,
+                      Buffers *keep = nullptr) {
+    // produce-only mode (fuse false, r0 null): piece sums and joined heads only
     Buffers B;
     B.own.assign(p->r, nullptr);
     B.ld_own.assign(p->r, 0);
@@ -167,7 +176,7 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
                 B.sigma[v] = items;
                 B.ld_sigma[v] = ld_items;
             }
-        } else {
+        } else if (fuse || r0) {
             RootArgs ra{};
             ra.groups = Rl.G;
             ra.n = p->n;
@@ -185,6 +194,7 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
             }
         }
     }
+    if (keep) *keep = B;
     if (!fuse || stop_before_tsqr) return FIGARO_OK;
     // post-processing TSQR over the stack
     int cur = 0;
@@ -202,9 +212,130 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
         a.final_r = R;
         {
             ProfScope ps(p, s, 5, 8.0 * (double)D.rows * p->n, 2.0 * (double)D.rows * p->n * p->n);
-            FIGARO_TRY(launch_dense(a, s));
+            FIGARO_TRY(launch_dense(a, p->variant, s));
         }
         cur = 1 - cur;
+    }
+    return FIGARO_OK;
+}
+
+struct Target {
+    double *p;
+    int64_t ld;
+};
+
+// Where the gradient of the key-group sums of relation v goes: the top level
+// of its heads_and_tails task, or the caller's value gradient if every key
+// group has one row.
+Target own_grad_target(figaro_plan_s *p, int v, double *const *dvalues, const int64_t *ld_dv) {
+    RelPlan &R = p->rel[v];
+    if (R.a2.active) return {R.a2.levels.back().d_gpieces, R.a2.levels.back().npieces};
+    return {dvalues[v], ld_dv[v]};
+}
+
+// Where the gradient of sigma_v (what relation v hands to its parent) goes.
+Target sigma_grad_target(figaro_plan_s *p, int v, double *const *dvalues, const int64_t *ld_dv) {
+    RelPlan &R = p->rel[v];
+    if (R.children.empty()) return own_grad_target(p, v, dvalues, ld_dv);
+    if (R.a4.active) return {R.a4.levels.back().d_gpieces, R.a4.levels.back().npieces};
+    return {R.d_gs, R.G};
+}
+
+// Backward of the levels of one task, top level first; level 0 writes the
+// gradient of the task's items to `out`.
+figaro_status run_task_bwd(figaro_plan_s *p, Task &T, const double *in, int64_t ld_in, Target out, hipStream_t s) {
+    for (int l = (int)T.levels.size() - 1; l >= 0; --l) {
+        Level &L = T.levels[l];
+        HelmertBwdArgs a{};
+        a.in = (l == 0) ? in : T.levels[l - 1].d_pieces;
+        a.ld_in = (l == 0) ? ld_in : T.levels[l - 1].npieces;
+        a.ncols = T.ncols;
+        a.pid = L.d_pid;
+        a.piece_start = L.d_piece_start;
+        a.phi_piece = L.d_phi_piece;
+        a.alpha = L.d_alpha;
+        a.beta = L.d_beta;
+        a.chunk_start = L.d_chunk_start;
+        a.nchunks = L.nchunks;
+        a.K = p->d_K;
+        a.n_total = p->n;
+        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (int8_t)T.cols[c];
+        a.gpieces = L.d_gpieces;
+        a.ld_gp = L.npieces;
+        a.gout = (l == 0) ? out.p : T.levels[l - 1].d_gpieces;
+        a.ld_gout = (l == 0) ? out.ld : T.levels[l - 1].npieces;
+        a.waves = (int32_t)std::min<int64_t>(L.nchunks, 8192);
+        ProfScope ps(p, s, 6, 8.0 * (double)L.items * T.ncols * 2.0, 2.0 * (double)L.items * T.ncols * T.ncols);
+        FIGARO_TRY(launch_helmert_bwd(a, L.unit, s));
+    }
+    return FIGARO_OK;
+}
+
+figaro_status backward(figaro_plan_s *p, const double *const *values, const int64_t *ld, const double *R,
+                       const double *dR, double *const *dvalues, const int64_t *ld_dv, hipStream_t s) {
+    // recompute the forward intermediates (piece sums, joined heads)
+    Buffers B;
+    figaro_status st = forward(p, values, ld, false, nullptr, nullptr, 0, nullptr, s, false, &B);
+    if (st != FIGARO_OK) return st;
+    {
+        ProfScope ps(p, s, 6, 0.0, 0.0);
+        FIGARO_TRY(launch_qr_adjoint(R, dR, p->n, p->d_K, p->d_status, s));
+    }
+    for (auto it = p->post.rbegin(); it != p->post.rend(); ++it) {   // parents before children
+        const int v = *it;
+        RelPlan &Rl = p->rel[v];
+        const bool leaf = Rl.children.empty();
+        // items of v after the join (s), and where their gradient lives
+        const double *items = leaf ? B.own[v] : Rl.d_s;
+        const int64_t ld_items = leaf ? B.ld_own[v] : Rl.G;
+        const Target gs = leaf ? own_grad_target(p, v, dvalues, ld_dv) : Target{Rl.d_gs, Rl.G};
+        if (Rl.parent < 0) {
+            RootBwdArgs ra{};
+            ra.groups = Rl.G;
+            ra.n = p->n;
+            ra.s = items;
+            ra.ld_s = ld_items;
+            ra.inv_sqrt_c = Rl.d_inv_sqrt_c;
+            ra.K = p->d_K;
+            ra.ds = gs.p;
+            ra.ld_ds = gs.ld;
+            ProfScope ps(p, s, 6, 16.0 * (double)Rl.G * p->n, 0.0);
+            FIGARO_TRY(launch_root_bwd(ra, s));
+        } else if (!leaf && Rl.a4.active) {
+            st = run_task_bwd(p, Rl.a4, items, ld_items, gs, s);
+            if (st != FIGARO_OK) return st;
+        }
+        if (!leaf) {
+            JoinBwdArgs j{};
+            j.groups = Rl.G;
+            j.ds = Rl.d_gs;
+            j.ld_ds = Rl.G;
+            const Target own = own_grad_target(p, v, dvalues, ld_dv);
+            j.dOwn = own.p;
+            j.ld_own = own.ld;
+            j.own_cols = Rl.ncols;
+            j.own_pos = Rl.own_pos;
+            j.own_mult = Rl.d_own_mult;
+            j.nchildren = (int32_t)Rl.children.size();
+            for (size_t c = 0; c < Rl.children.size(); ++c) {
+                const int ch = Rl.children[c];
+                const Target t = sigma_grad_target(p, ch, dvalues, ld_dv);
+                j.dsigma[c] = t.p;
+                j.ld_dsigma[c] = t.ld;
+                j.child_groups[c] = p->rel[ch].P;
+                j.child_cols[c] = p->rel[ch].nsub;
+                j.colpos[c] = Rl.d_colpos[c];
+                j.inv_off[c] = Rl.d_inv_off[c];
+                j.inv_idx[c] = Rl.d_inv_idx[c];
+                j.mult[c] = Rl.d_mult[c];
+            }
+            ProfScope ps(p, s, 6, 16.0 * (double)Rl.G * Rl.nsub, 0.0);
+            FIGARO_TRY(launch_join_bwd(j, s));
+        }
+        if (Rl.a2.active) {
+            st = run_task_bwd(p, Rl.a2, values[v], ld[v], Target{dvalues[v], ld_dv[v]}, s);
+            if (st != FIGARO_OK) return st;
+        }
     }
     return FIGARO_OK;
 }
@@ -212,6 +343,28 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
 }  // namespace
 
 extern "C" {
+
+figaro_status figaro_r_backward(figaro_plan_t p, const double *const *values, const int64_t *ld, const double *R,
+                                const double *dR, double *const *dvalues, const int64_t *ld_dvalues,
+                                hipStream_t stream) {
+    if (!p) return set_error(nullptr, FIGARO_EINVAL, "plan is NULL");
+    if (!R || !dR || !dvalues || !ld_dvalues) return set_error(p, FIGARO_EINVAL, "NULL argument");
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    for (int i = 0; i < p->r; ++i)
+        if (!dvalues[i] || ld_dvalues[i] < p->rel[i].m)
+            return set_error(p, FIGARO_EINVAL, "dvalues[" + std::to_string(i) + "] is NULL or its ld too small");
+    return backward(p, values, ld, R, dR, dvalues, ld_dvalues, stream);
+}
+
+figaro_status figaro_backward_status(figaro_plan_t p, hipStream_t stream) {
+    if (!p || p->analyze_only) return set_error(p, FIGARO_EINVAL, "bad argument");
+    int32_t st = 0;
+    if (hipMemcpyAsync(&st, p->d_status, sizeof(int32_t), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return set_error(p, FIGARO_EHIP, "reading the backward status failed");
+    return st ? set_error(p, FIGARO_ESINGULAR, "R has a zero diagonal entry") : FIGARO_OK;
+}
 
 figaro_status figaro_r(figaro_plan_t p, const double *const *values, const int64_t *ld, double *R,
                        hipStream_t stream) {
@@ -260,6 +413,37 @@ figaro_status figaro_unpermute_values(figaro_plan_t p, int32_t rel, const double
 }
 
 int64_t figaro_debug_stack_rows(figaro_plan_t p) { return p ? p->stack_rows : -1; }
+
+int32_t figaro_debug_stack_layout(figaro_plan_t p, int64_t *out, int32_t max_regions) {
+    if (!p || !out) return -1;
+    int32_t k = 0;
+    for (int v : p->post) {
+        RelPlan &R = p->rel[v];
+        for (Task *T : {&R.a2, &R.a4}) {
+            if (!T->active) continue;
+            for (size_t l = 0; l < T->levels.size(); ++l) {
+                const Level &L = T->levels[l];
+                const int64_t rows = (l == 0) ? (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols
+                                              : L.items;
+                if (k < max_regions) {
+                    out[3 * k] = T->block_id;
+                    out[3 * k + 1] = L.stack_row0;
+                    out[3 * k + 2] = rows;
+                }
+                ++k;
+            }
+        }
+        if (R.parent < 0) {
+            if (k < max_regions) {
+                out[3 * k] = 3 * v + 2;
+                out[3 * k + 1] = R.root_row0;
+                out[3 * k + 2] = R.G;
+            }
+            ++k;
+        }
+    }
+    return k;
+}
 
 figaro_status figaro_debug_stack(figaro_plan_t p, const double *const *values, const int64_t *ld, double *host_out,
                                  hipStream_t stream) {

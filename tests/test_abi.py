@@ -59,7 +59,7 @@ def test_plan_rejects_malformed_trees(spec, status):
     L = F.lib()
     arr, keep = _descs(spec)
     h = ctypes.c_void_p()
-    opts = F.PlanOptions(0, 0, 1, 1)
+    opts = F.PlanOptions(0, 0, 1, 0, 1)
     st = L.figaro_plan_create(ctypes.byref(h), len(spec), arr, ctypes.byref(opts), None)
     assert F.STATUS_NAMES[st] == status
     assert not h.value

@@ -1,0 +1,186 @@
+"""Parity of the hand-written adjoint with autograd through the QR of the
+materialised join (CPU, FP64), closed forms and central finite differences
+(needs an MI355X).  Gradients must match within 1e-6 relative of finite
+differences and (much tighter) of autograd."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _relf(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_00525_amd as F
+    F.lib()
+    return F
+
+
+def gpu_grads(F, inst, loss_fn, **kw):
+    """Gradients (caller row order, numpy) of loss_fn(R) through FigaroR."""
+    import torch
+    plan = F.plan_from_instance(inst, **kw)
+    vals = [v.clone().requires_grad_(True) for v in F.device_values(plan, inst)]
+    R = F.figaro_r(plan, *vals)
+    L = loss_fn(R)
+    L.backward()
+    torch.cuda.synchronize()
+    out = [plan.from_plan_order(i, vals[i].grad.detach()).cpu().numpy() for i in range(inst.r)]
+    return out, R.detach().cpu().numpy(), plan
+
+
+CASES = {
+    "config1": lambda: synth.config1(),
+    "paper_fig3_b": lambda: synth.paper_fig3(5, m=(40, 90, 30, 30), n=(3, 2, 4, 1), dom=3),
+    "chain4": lambda: synth.random_chain(4, 4, 40, 2, 4),
+    "star_pk": lambda: synth.random_star(5, 4, 600, 30, 3),
+    "star_nonpk": lambda: synth.random_star(6, 3, 300, 40, 2, pk_dims=False, dom=10),
+    "star_dim_root": lambda: synth.random_star(7, 4, 500, 20, 2, root=2),
+    "two_rel_zipf": lambda: synth.two_relation(10, 3000, 3000, 6, 5, 60, dist="zipf"),
+    "config4_div1000": lambda: synth.config3(seed=1004, div=1000),
+    "cartesian": lambda: synth.cartesian_uniform(8, 60, 3, 50, 2),
+}
+
+
+def _weighted(n, seed):
+    rng = np.random.default_rng(seed)
+    return np.triu(rng.standard_normal((n, n)))
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_backward_matches_autograd(F, oracle_lib, name):
+    import torch
+    inst = CASES[name]()
+    W = _weighted(inst.n, 7)
+    Wt = torch.as_tensor(W)
+    _say(f"[backward] case={name} n={inst.n} M={inst.M}")
+    g, R, plan = gpu_grads(F, inst, lambda R: (R * Wt.to(R.device)).sum())
+    ref, Rref = oracle_lib.grad_autograd(inst, lambda R: (R * Wt).sum())
+    assert _relf(R, Rref) <= 1e-10
+    errs = [_relf(a, b) for a, b in zip(g, ref)]
+    _say(f"[backward] case={name} rel_errs={['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-8
+
+
+def config4_loss(R):
+    """Least-squares residual of the last column on the others plus the
+    log-determinant: 1/2 R_nn^2 + sum_i log R_ii."""
+    import torch
+    d = torch.diagonal(R)
+    return 0.5 * R[-1, -1] ** 2 + torch.log(d).sum()
+
+
+@pytest.mark.parametrize("tile", [0, 64])
+def test_backward_config4_loss(F, oracle_lib, tile):
+    inst = CASES["config4_div1000"]()
+    g, R, plan = gpu_grads(F, inst, config4_loss, tile_items=tile)
+    ref, _ = oracle_lib.grad_autograd(inst, config4_loss)
+    errs = [_relf(a, b) for a, b in zip(g, ref)]
+    _say(f"[backward] config4 tile={tile} rel_errs={['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-8
+
+
+def test_backward_logdet_closed_form(F, oracle_lib):
+    import torch
+    inst = CASES["star_nonpk"]()
+    g, R, plan = gpu_grads(F, inst, lambda R: torch.log(torch.diagonal(R)).sum())
+    ref = oracle_lib.grad_logdet_closed_form(inst)
+    assert max(_relf(a, b) for a, b in zip(g, ref)) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["paper_fig3_b", "two_rel_zipf", "star_nonpk"])
+def test_backward_central_differences(F, name):
+    """Central finite differences of the GPU forward pass itself, on random
+    coordinates of every relation."""
+    import torch
+    inst = CASES[name]()
+    plan = F.plan_from_instance(inst)
+    vals = F.device_values(plan, inst)
+    W = torch.as_tensor(_weighted(inst.n, 3), device="cuda")
+
+    def loss(vs):
+        return float((plan.r_factor(vs) * W).sum().item())
+
+    vg = [v.clone().requires_grad_(True) for v in vals]
+    R = F.figaro_r(plan, *vg)
+    (R * W).sum().backward()
+    rng = np.random.default_rng(0)
+    num, ana = [], []
+    for i in range(inst.r):
+        for _ in range(6):
+            c = int(rng.integers(0, vals[i].shape[0]))
+            t = int(rng.integers(0, vals[i].shape[1]))
+            h = 1e-6 * max(1.0, abs(float(vals[i][c, t])))
+            vp = [v.clone() for v in vals]
+            vm = [v.clone() for v in vals]
+            vp[i][c, t] += h
+            vm[i][c, t] -= h
+            num.append((loss(vp) - loss(vm)) / (2 * h))
+            ana.append(float(vg[i].grad[c, t]))
+    num, ana = np.array(num), np.array(ana)
+    err = np.linalg.norm(num - ana) / np.linalg.norm(ana)
+    _say(f"[backward-fd] case={name} rel_err={err:.2e}")
+    assert err <= 1e-6
+
+
+def test_backward_split_tiles_same_gradient(F):
+    import torch
+    inst = CASES["two_rel_zipf"]()
+    W = torch.as_tensor(_weighted(inst.n, 9))
+    g0, _, _ = gpu_grads(F, inst, lambda R: (R * W.to(R.device)).sum())
+    g1, _, _ = gpu_grads(F, inst, lambda R: (R * W.to(R.device)).sum(), tile_items=64, waves_per_task=5)
+    assert max(_relf(a, b) for a, b in zip(g1, g0)) <= 1e-10
+
+
+def test_backward_deterministic(F):
+    import torch
+    inst = CASES["star_pk"]()
+    plan = F.plan_from_instance(inst)
+    vals = F.device_values(plan, inst)
+    R = plan.r_factor(vals)
+    dR = torch.as_tensor(_weighted(inst.n, 1), device="cuda")
+    a = [x.cpu().numpy() for x in plan.r_backward(vals, R, dR)]
+    b = [x.cpu().numpy() for x in plan.r_backward(vals, R, dR)]
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def test_backward_dropped_rows_get_zero(F, oracle_lib):
+    import torch
+    inst = synth.two_relation(14, 500, 400, 3, 2, 40)
+    inst.rels[0].keys[0, :25] = 1000 + np.arange(25)
+    W = torch.as_tensor(_weighted(inst.n, 2))
+    g, R, plan = gpu_grads(F, inst, lambda R: (R * W.to(R.device)).sum())
+    assert np.all(g[0][:, :25] == 0.0)
+    ref, _ = oracle_lib.grad_autograd(inst, lambda R: (R * W).sum())
+    assert max(_relf(a, b) for a, b in zip(g, ref)) <= 1e-8
+
+
+def test_backward_singular_status(F):
+    import torch
+    inst = synth.two_relation(15, 300, 200, 3, 2, 20)
+    inst.rels[0].values[1, :] = 0.0          # a zero column: R has a zero diagonal entry
+    plan = F.plan_from_instance(inst)
+    vals = F.device_values(plan, inst)
+    R = plan.r_factor(vals)
+    plan.r_backward(vals, R, torch.eye(inst.n, device="cuda", dtype=torch.float64))
+    assert plan.backward_status() == "ESINGULAR"
+    inst2 = synth.two_relation(15, 300, 200, 3, 2, 20)
+    plan2 = F.plan_from_instance(inst2)
+    vals2 = F.device_values(plan2, inst2)
+    plan2.r_backward(vals2, plan2.r_factor(vals2), torch.eye(inst2.n, device="cuda", dtype=torch.float64))
+    assert plan2.backward_status() == "OK"

@@ -233,3 +233,13 @@ def test_counts_match_definitions(F, oracle_lib, maker):
             for kind in ("phi_up", "phi_down"):
                 got = plan.counts(i, kind)
                 assert [cnt[i][kind][k] for k in pk] == got.tolist(), (i, kind)
+
+
+@pytest.mark.parametrize("name", ["config1", "config2_div1000", "config3_div1000", "two_rel_zipf", "chain4_zipf",
+                                  "star_nonpk"])
+@pytest.mark.parametrize("tile", [0, 64])
+def test_forward_variant1(F, oracle_lib, name, tile):
+    """The alternative tile shape (two waves per SIMD) gives the same R."""
+    inst = CASES[name]()
+    R, plan, _ = gpu_r(F, inst, variant=1, tile_items=tile)
+    assert _relf(R, oracle_lib.r_of_join(inst)) <= TOL
