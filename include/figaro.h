@@ -98,7 +98,9 @@ typedef struct {
     int32_t variant;            /* form of the register-tile Householder QR:
                                    0 fully unrolled (triangular work), 1
                                    compact runtime column loop (smaller code,
-                                   twice the arithmetic) */
+                                   twice the arithmetic), 2 fully unrolled
+                                   with a register budget for two waves per
+                                   SIMD; other values give FIGARO_EINVAL */
     int32_t analyze_only;       /* 1: stop after the count queries; the plan
                                    then answers the info and count queries
                                    only, holds no device memory, and the

@@ -197,6 +197,7 @@ hipError_t launch_copy_cols(const double *src, int64_t ld_src, double *dst, int6
                             int32_t ncols, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 int tile_items_for(int ncols, int variant);   // items per chunk of the register-tile kernel
+int num_variants();                           // number of register-tile kernel variants
 int dense_tile_rows_for(int ncols);   // rows per tile of the dense kernel
 int waves_per_block();                // waves per workgroup of the QR kernels
 

@@ -56,167 +56,184 @@ __device__ __forceinline__ double row_sum16(double v) {
     return v;
 }
 
+// Same reduction, leaving every total in every lane (vector registers):
+// after the row sums, register q holds the four totals of a group in its four
+// 16-lane rows; a permlane16 swap of q with itself spreads them to lane
+// halves, and a permlane32 swap of each half with itself to the whole wave.
+__device__ __forceinline__ void spread4(double q, double &a, double &b, double &c, double &d) {
+    // rows of q: [a, c, b, d]
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(q), (unsigned)__double2loint(q),
+                                                     false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(q), (unsigned)__double2hiint(q),
+                                                     false, false);
+    // lo[0]/hi[0] rows: [a, a, b, b]; lo[1]/hi[1] rows: [c, c, d, d]
+    const auto l0 = __builtin_amdgcn_permlane32_swap(lo[0], lo[0], false, false);
+    const auto h0 = __builtin_amdgcn_permlane32_swap(hi[0], hi[0], false, false);
+    const auto l1 = __builtin_amdgcn_permlane32_swap(lo[1], lo[1], false, false);
+    const auto h1 = __builtin_amdgcn_permlane32_swap(hi[1], hi[1], false, false);
+    // permlane32 swap of r with itself: [0] = its lower half everywhere, [1] = its upper half
+    a = __hiloint2double((int)h0[0], (int)l0[0]);
+    b = __hiloint2double((int)h0[1], (int)l0[1]);
+    c = __hiloint2double((int)h1[0], (int)l1[0]);
+    d = __hiloint2double((int)h1[1], (int)l1[1]);
+}
+
 template <int C>
 __device__ __forceinline__ void wave_sum_batch(double *v) {
-    if constexpr (C == 1) {
-        v[0] = wave_sum(v[0]);
-    } else {
-        constexpr int C2 = (C + 1) / 2;
-        constexpr int C4 = (C2 + 1) / 2;
-        double h[C2];
+    constexpr int C2 = (C + 1) / 2;
+    constexpr int C4 = (C2 + 1) / 2;
+    double h[C2];
 #pragma unroll
-        for (int i = 0; i < C2; ++i) h[i] = swap32_add(v[2 * i], (2 * i + 1 < C) ? v[2 * i + 1] : 0.0);
-        double q[C4];
+    for (int i = 0; i < C2; ++i) h[i] = swap32_add(v[2 * i], (2 * i + 1 < C) ? v[2 * i + 1] : 0.0);
 #pragma unroll
-        for (int i = 0; i < C4; ++i) q[i] = row_sum16(swap16_add(h[2 * i], (2 * i + 1 < C2) ? h[2 * i + 1] : 0.0));
-        // row 0 of q[i] holds value 4i, row 1 value 4i+2, row 2 value 4i+1, row 3 value 4i+3
-#pragma unroll
-        for (int i = 0; i < C4; ++i) {
-            v[4 * i] = lane_value(q[i], 0);
-            if (4 * i + 1 < C) v[4 * i + 1] = lane_value(q[i], 32);
-            if (4 * i + 2 < C) v[4 * i + 2] = lane_value(q[i], 16);
-            if (4 * i + 3 < C) v[4 * i + 3] = lane_value(q[i], 48);
-        }
+    for (int i = 0; i < C4; ++i) {
+        const double q = row_sum16(swap16_add(h[2 * i], (2 * i + 1 < C2) ? h[2 * i + 1] : 0.0));
+        double t0, t1, t2, t3;
+        spread4(q, t0, t1, t2, t3);
+        v[4 * i] = t0;
+        if (4 * i + 1 < C) v[4 * i + 1] = t1;
+        if (4 * i + 2 < C) v[4 * i + 2] = t2;
+        if (4 * i + 3 < C) v[4 * i + 3] = t3;
     }
 }
 
-// One Householder step per column j of the stacked matrix [R; X], where R is
-// held one row per lane (lane l holds row l, lanes >= NB hold zero rows) and X
-// holds RPL rows per lane.  The reflector of column j acts on the pivot row
-// (row j of R, lane j), the rows of R below it and every row of X.  It is
-// generated as in LAPACK's dlarfg: with p the pivot row, x the column below
-// the pivot and D_k = x . B_k over the non-pivot rows,
-//   beta = -sign(p_j) sqrt(p_j^2 + ||x||^2),  tau = (beta - p_j) / beta,
-//   v = [1; x / (p_j - beta)],                w_k = p_k + D_k / (p_j - beta),
-//   pivot row: B_jk -= tau w_k;  other rows: B_ik -= tau w_k x_i / (p_j - beta),
-// and the step is skipped (H = I) when ||x|| = 0.  No quantity here can
-// overflow when the column below the pivot is tiny (rank-deficient tiles).
+// Reciprocal by the hardware estimate refined with two Newton iterations
+// (r <- r + r (1 - x r)); x is a normal number here.
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Householder reflector of one column of [R; X] (LAPACK dlarfg form): with p
+// the pivot R_jj and x2 = ||X_j||^2 > 0,
+//   beta = -sign(p) sqrt(p^2 + x2),  tau = (beta - p) / beta,  scale = 1 / (p - beta),
+// so that v = [1; X_j * scale] and H = I - tau v v^T.  For x2 = 0 the
+// reflector is the identity (tau = 0) and R_jj stays p.  Branch-free.
+struct Reflector {
+    double tau, scale, ts, rjj;
+};
+
+__device__ __forceinline__ Reflector reflector(double p, double x2) {
+    const bool act = x2 > 0.0;
+    const double nrm = sqrt(fma(p, p, x2));
+    const double beta = (p >= 0.0) ? -nrm : nrm;
+    const double den = act ? (p - beta) : 1.0;    // p - beta, |p - beta| >= nrm
+    const double bden = act ? beta : 1.0;
+    const double inv_b = recip(bden);
+    Reflector h;
+    h.scale = recip(den);
+    h.tau = act ? -den * inv_b : 0.0;               // (beta - p) / beta
+    h.ts = act ? -inv_b : 0.0;                      // tau * scale
+    h.rjj = act ? beta : p;
+    return h;
+}
+
+// One Householder step per column J of the stacked matrix [R; X]: R (NB x NB
+// upper triangular, row-major in the wave's LDS slice) on top of the tile X
+// (RPL rows per lane).  Because R is triangular, the reflector of column J
+// touches only row J of R and the rows of X: with D_k = X_J . X_k and p the
+// old row J,
+//   w_k = p_k + scale D_k,   X_k -= tau scale w_k X_J,   R_Jk = p_k - tau w_k,
+// and R_JJ = beta.  Row J is read once and written once per tile; every lane
+// reads and writes the same LDS words (broadcast).
 template <int NB, int RPL, int J>
-__device__ __forceinline__ void qr_column(double (&x)[RPL][NB], double (&rs)[NB], int lane) {
+__device__ __forceinline__ void qr_column(double (&x)[RPL][NB], double *rw) {
     constexpr int C = NB - J;
     double d[C];
-    const bool below = lane > J;
 #pragma unroll
     for (int k = J; k < NB; ++k) {
-        double acc = below ? rs[J] * rs[k] : 0.0;
+        double acc = 0.0;
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc = fma(x[r][J], x[r][k], acc);
         d[k - J] = acc;
     }
-    wave_sum_batch<C>(d);
     double p[C];
 #pragma unroll
-    for (int k = J; k < NB; ++k) p[k - J] = lane_value(rs[k], J);
-    const double xn2 = d[0];
-    if (xn2 > 0.0) {
-        const double pj = p[0];
-        const double nrm = sqrt(fma(pj, pj, xn2));
-        const double beta = (pj >= 0.0) ? -nrm : nrm;
-        const double tau = (beta - pj) / beta;
-        const double scale = 1.0 / (pj - beta);
-        const double ts = tau * scale;
-        const double vo = below ? rs[J] : 0.0;
+    for (int k = J; k < NB; ++k) p[k - J] = rw[J * NB + k];
+    wave_sum_batch<C>(d);
+    const Reflector h = reflector(p[0], d[0]);
 #pragma unroll
-        for (int k = J + 1; k < NB; ++k) {
-            const double w = fma(scale, d[k - J], p[k - J]);
-            const double g = ts * w;
+    for (int k = J + 1; k < NB; ++k) {
+        const double w = fma(h.scale, d[k - J], p[k - J]);
+        const double g = h.ts * w;
 #pragma unroll
-            for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][J], x[r][k]);
-            rs[k] = (lane == J) ? fma(-tau, w, rs[k]) : fma(-g, vo, rs[k]);
-        }
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) x[r][J] = 0.0;
-        if (lane == J) rs[J] = beta;
-        else if (below) rs[J] = 0.0;
+        for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][J], x[r][k]);
+        rw[J * NB + k] = fma(-h.tau, w, p[k - J]);
     }
+    rw[J * NB + J] = h.rjj;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) x[r][J] = 0.0;
 }
 
 template <int NB, int RPL, int... Js>
-__device__ __forceinline__ void qr_columns(double (&x)[RPL][NB], double (&rs)[NB], int lane,
-                                           std::integer_sequence<int, Js...>) {
-    (qr_column<NB, RPL, Js>(x, rs, lane), ...);
-}
-
-template <int NB, int RPL>
-__device__ __forceinline__ void qr_accumulate(double (&x)[RPL][NB], double (&rs)[NB], int lane) {
-    qr_columns<NB, RPL>(x, rs, lane, std::make_integer_sequence<int, NB>{});
+__device__ __forceinline__ void qr_columns(double (&x)[RPL][NB], double *rw, std::integer_sequence<int, Js...>) {
+    (qr_column<NB, RPL, Js>(x, rw), ...);
 }
 
 // Same step for wide tiles with a runtime column loop: the pivot column is
 // always register column 0 and every step rotates the columns left by one, so
-// after NB steps every column is back in place.  Columns already eliminated
-// are zero on the rows the later reflectors act on and are left unchanged.
+// after NB steps every column is back in place.  At step j register column k
+// holds column j + k (mod NB); the columns that wrap around are already
+// eliminated (zero in X and below the diagonal of R), so their update is
+// the identity.
 template <int NB, int RPL>
-__device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double (&rs)[NB], int lane) {
+__device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *rw) {
     for (int j = 0; j < NB; ++j) {
-        const bool below = lane > j;
         double d[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            double acc = below ? rs[0] * rs[k] : 0.0;
+            double acc = 0.0;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) acc = fma(x[r][0], x[r][k], acc);
             d[k] = acc;
         }
-        wave_sum_batch<NB>(d);
         double p[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) p[k] = lane_value(rs[k], j);
-        const double xn2 = d[0];
-        if (xn2 > 0.0) {
-            const double pj = p[0];
-            const double nrm = sqrt(fma(pj, pj, xn2));
-            const double beta = (pj >= 0.0) ? -nrm : nrm;
-            const double tau = (beta - pj) / beta;
-            const double scale = 1.0 / (pj - beta);
-            const double ts = tau * scale;
-            const double vo = below ? rs[0] : 0.0;
+        for (int k = 0; k < NB; ++k) p[k] = (k < NB - j) ? rw[j * NB + j + k] : 0.0;
+        wave_sum_batch<NB>(d);
+        const Reflector h = reflector(p[0], d[0]);
 #pragma unroll
-            for (int k = 1; k < NB; ++k) {
-                const double w = fma(scale, d[k], p[k]);
-                const double g = ts * w;
+        for (int k = 1; k < NB; ++k) {
+            const double w = fma(h.scale, d[k], p[k]);
+            const double g = h.ts * w;
 #pragma unroll
-                for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][0], x[r][k]);
-                rs[k] = (lane == j) ? fma(-tau, w, rs[k]) : fma(-g, vo, rs[k]);
-            }
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) x[r][0] = 0.0;
-            if (lane == j) rs[0] = beta;
-            else if (below) rs[0] = 0.0;
+            for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][0], x[r][k]);
+            if (k < NB - j) rw[j * NB + j + k] = fma(-h.tau, w, p[k]);
         }
-        // rotate columns left by one
+        rw[j * NB + j] = h.rjj;
+        // rotate columns left by one (column j is zero now)
 #pragma unroll
         for (int r = 0; r < RPL; ++r) {
-            const double t = x[r][0];
 #pragma unroll
             for (int k = 0; k < NB - 1; ++k) x[r][k] = x[r][k + 1];
-            x[r][NB - 1] = t;
+            x[r][NB - 1] = 0.0;
         }
-        const double t = rs[0];
-#pragma unroll
-        for (int k = 0; k < NB - 1; ++k) rs[k] = rs[k + 1];
-        rs[NB - 1] = t;
     }
 }
 
 // ROT selects the compact runtime-loop form (code size O(NB) instead of
 // O(NB^2), at twice the arithmetic); wide tiles always use it.
 template <int NB, int RPL, bool ROT = false>
-__device__ __forceinline__ void qr_step(double (&x)[RPL][NB], double (&rs)[NB], int lane) {
-    if constexpr (NB <= 32 && !ROT) qr_accumulate<NB, RPL>(x, rs, lane);
-    else qr_accumulate_rot<NB, RPL>(x, rs, lane);
+__device__ __forceinline__ void qr_step(double (&x)[RPL][NB], double *rw) {
+    if constexpr (NB <= 32 && !ROT) qr_columns<NB, RPL>(x, rw, std::make_integer_sequence<int, NB>{});
+    else qr_accumulate_rot<NB, RPL>(x, rw);
 }
 
-// Merging the running R factors of the waves of a workgroup into wave 0:
-// the other waves write their R rows to LDS (rows padded to NB+1 doubles to
-// spread LDS banks) and wave 0 folds them in as extra tiles through the same
-// QR call site as the data tiles (one copy of the QR code per kernel).
+// Each wave keeps its running R in its own LDS slice (NB x NB doubles,
+// row-major, zero below the diagonal).  Merging the waves of a workgroup:
+// after a barrier, wave 0 folds the R factors of waves 1..3 in as extra
+// tiles through the same QR call site as the data tiles.
 template <int NB>
-__device__ __forceinline__ void merge_publish(const double (&rs)[NB], int lane, int wib, double *lds) {
-    if (wib > 0 && lane < NB) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c) lds[((wib - 1) * NB + lane) * (NB + 1) + c] = rs[c];
-    }
+constexpr int r_slice_doubles() {
+    return NB * NB;
+}
+
+template <int NB>
+__device__ __forceinline__ void r_zero(double *rw, int lane) {
+    for (int i = lane; i < NB * NB; i += 64) rw[i] = 0.0;
 }
 
 template <int NB, int RPL>
@@ -225,8 +242,10 @@ __device__ __forceinline__ void merge_load(double (&x)[RPL][NB], int lane, int t
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
         const int r = t0 + lane * RPL + k;
+        // row r of the merge block: row (r % NB) of wave 1 + r / NB
+        const int src = (r < ROWS) ? (NB * NB + r * NB) : 0;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) x[k][c] = (r < ROWS) ? lds[r * (NB + 1) + c] : 0.0;
+        for (int c = 0; c < NB; ++c) x[k][c] = (r < ROWS) ? lds[src + c] : 0.0;
     }
 }
 
@@ -235,20 +254,15 @@ constexpr int merge_tiles() {
     return ((kWavesPerBlock - 1) * NB + 64 * RPL - 1) / (64 * RPL);
 }
 
+// Write the R (rows 0..ncols-1) of a workgroup into the stack, spreading
+// local column c to global column colmap[c]; other columns get 0.
 template <int NB>
-constexpr int merge_lds_doubles() {
-    return (kWavesPerBlock - 1) * NB * (NB + 1);
-}
-
-// Write the running R (rows 0..ncols-1) of a workgroup into the stack,
-// spreading local column c to global column colmap[c]; other columns get 0.
-template <int NB>
-__device__ __forceinline__ void store_r(const HelmertArgs &a, const double (&rs)[NB], int lane, int64_t slot) {
+__device__ __forceinline__ void store_r(const HelmertArgs &a, const double *rw, int lane, int64_t slot) {
     if (lane >= a.ncols) return;
     const int64_t row = a.stack_row0 + slot * a.ncols + lane;
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-        if (c < a.ncols) a.stack[(int64_t)a.colmap[c] * a.ld_stack + row] = rs[c];
+        if (c < a.ncols) a.stack[(int64_t)a.colmap[c] * a.ld_stack + row] = rw[lane * NB + c];
     for (uint64_t m = a.other_cols; m; m &= m - 1)
         a.stack[(int64_t)__builtin_ctzll(m) * a.ld_stack + row] = 0.0;
 }
@@ -258,14 +272,14 @@ __device__ __forceinline__ void store_r(const HelmertArgs &a, const double (&rs)
 // the running R of the wave, merge the waves of the workgroup and write one R
 // per workgroup; otherwise write the tail rows to the R0 buffer.
 //
-// Merge protocol (FUSE): waves 1..3 publish their R to LDS after their data
-// chunks and wait at the barrier; wave 0 waits at the same barrier once its
-// data chunks are done and then folds the published factors in as extra
-// tiles through the same QR call site.  Every wave executes exactly one
-// barrier and all branches around it are uniform within a wave.
+// Merge protocol (FUSE): each wave accumulates into its own LDS slice; waves
+// 1..3 wait at the barrier after their data chunks; wave 0 waits at the same
+// barrier once its data chunks are done and then folds the other slices in
+// as extra tiles through the same QR call site.  Every wave executes exactly
+// one barrier and all branches around it are uniform within a wave.
 template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
-    __shared__ double lds[FUSE ? merge_lds_doubles<NB>() : 1];
+    __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB>() : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int wave = blockIdx.x * kWavesPerBlock + wib;
@@ -273,9 +287,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     if (!FUSE && !active) return;
     const int64_t c_begin = active ? a.nchunks * wave / a.waves : 0;
     const int64_t c_end = active ? a.nchunks * (wave + 1) / a.waves : 0;
-    double rs[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) rs[c] = 0.0;
+    double *rw = lds + (FUSE ? wib * r_slice_doubles<NB>() : 0);
+    if constexpr (FUSE) r_zero<NB>(rw, lane);
     const int64_t n_data = c_end - c_begin;
     const int64_t n_iter = n_data + ((FUSE && wib == 0) ? merge_tiles<NB, RPL>() : 0);
 
@@ -378,15 +391,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                 continue;
             }
         }
-        if constexpr (FUSE) qr_step<NB, RPL, ROT>(x, rs, lane);
+        if constexpr (FUSE) qr_step<NB, RPL, ROT>(x, rw);
     }
     if constexpr (FUSE) {
-        if (wib > 0) {
-            merge_publish<NB>(rs, lane, wib, lds);
-            __syncthreads();
-        } else {
-            store_r<NB>(a, rs, lane, blockIdx.x);
-        }
+        if (wib > 0) __syncthreads();
+        else store_r<NB>(a, rw, lane, blockIdx.x);
     }
 }
 
@@ -394,16 +403,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
 // per tile, tpw tiles per wave) into one R and writes it to rows b*n..b*n+n-1
 // of `out`; with a single workgroup, the sign-normalised R goes to final_r.
 // Same merge protocol as k_helmert.
-template <int NB, int RPL, bool ROT>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_dense(DenseArgs a) {
-    __shared__ double lds[merge_lds_doubles<NB>()];
+template <int NB, int RPL, bool ROT, int OCC>
+__global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a) {
+    __shared__ double lds[kWavesPerBlock * r_slice_doubles<NB>()];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     constexpr int T = 64 * RPL;
-    double rs[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) rs[c] = 0.0;
+    double *rw = lds + wib * r_slice_doubles<NB>();
+    r_zero<NB>(rw, lane);
     const int64_t n_data = a.tiles_per_wave;
     const int64_t n_iter = n_data + ((wib == 0) ? merge_tiles<NB, RPL>() : 0);
     for (int64_t it = 0; it < n_iter; ++it) {
@@ -421,28 +429,23 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_dense(DenseArgs a) {
                 for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? col[base + k] : 0.0;
             }
         }
-        qr_step<NB, RPL, ROT>(x, rs, lane);
+        qr_step<NB, RPL, ROT>(x, rw);
     }
     if (wib > 0) {
-        merge_publish<NB>(rs, lane, wib, lds);
         __syncthreads();
         return;
     }
     if (lane >= a.n) return;
     if (a.waves == 1 && a.final_r) {
-        double diag = 0.0;
+        const double sg = (rw[lane * NB + lane] < 0.0) ? -1.0 : 1.0;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-            if (c == lane) diag = rs[c];
-        const double sg = (diag < 0.0) ? -1.0 : 1.0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            if (c < a.n) a.final_r[(int64_t)c * a.n + lane] = (c >= lane) ? sg * rs[c] : 0.0;
+            if (c < a.n) a.final_r[(int64_t)c * a.n + lane] = (c >= lane) ? sg * rw[lane * NB + c] : 0.0;
     } else {
         const int64_t row = (int64_t)blockIdx.x * a.n + lane;
 #pragma unroll
         for (int c = 0; c < NB; ++c)
-            if (c < a.n) a.out[(int64_t)c * a.ld_out + row] = rs[c];
+            if (c < a.n) a.out[(int64_t)c * a.ld_out + row] = rw[lane * NB + c];
     }
 }
 
@@ -503,22 +506,18 @@ int nb_for(int ncols) {
 }
 
 // Tile shapes of the head/tail + QR kernel: rows per lane (RPL), minimum
-// resident waves per SIMD the register budget is built for, and the QR form
-// (ROT: compact runtime column loop; otherwise fully unrolled triangular).
-// variant 0: unrolled; variant 1: compact.
+// resident waves per SIMD the register budget is built for (OCC), and the QR
+// form (ROT: compact runtime column loop; otherwise fully unrolled
+// triangular).  variant 0: unrolled, one wave per SIMD; 1: compact; 2:
+// unrolled, two waves per SIMD.
 template <int NB, int V>
-struct Shape;
-template <> struct Shape<8, 0> { static constexpr int RPL = 8, OCC = 1; static constexpr bool ROT = false; };
-template <> struct Shape<8, 1> { static constexpr int RPL = 8, OCC = 1; static constexpr bool ROT = true; };
-template <> struct Shape<16, 0> { static constexpr int RPL = 4, OCC = 1; static constexpr bool ROT = false; };
-template <> struct Shape<16, 1> { static constexpr int RPL = 4, OCC = 1; static constexpr bool ROT = true; };
-template <> struct Shape<32, 0> { static constexpr int RPL = 2, OCC = 1; static constexpr bool ROT = false; };
-template <> struct Shape<32, 1> { static constexpr int RPL = 2, OCC = 1; static constexpr bool ROT = true; };
-template <> struct Shape<64, 0> { static constexpr int RPL = 1, OCC = 1; static constexpr bool ROT = true; };
-template <> struct Shape<64, 1> { static constexpr int RPL = 1, OCC = 1; static constexpr bool ROT = true; };
+struct Shape {
+    static constexpr int RPL = NB <= 8 ? 8 : NB <= 16 ? 4 : NB <= 32 ? 2 : 1;
+    static constexpr int OCC = (V == 2 && NB <= 32) ? 2 : 1;
+    static constexpr bool ROT = V == 1 || NB > 32;
+};
 
-template <int NB>
-constexpr int rpl_for() { return Shape<NB, 0>::RPL; }
+constexpr int kVariants = 3;
 
 template <int NB, int V>
 hipError_t helmert_nb(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s) {
@@ -537,45 +536,61 @@ hipError_t helmert_nb(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s)
 
 template <int NB, int V>
 hipError_t dense_nb(const DenseArgs &a, hipStream_t s) {
-    constexpr int RPL = Shape<NB, V>::RPL;
+    constexpr int RPL = Shape<NB, V>::RPL, OCC = Shape<NB, V>::OCC;
     dim3 grid(a.waves), block(64 * kWavesPerBlock);
-    hipLaunchKernelGGL((k_dense<NB, RPL, Shape<NB, V>::ROT>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_dense<NB, RPL, Shape<NB, V>::ROT, OCC>), grid, block, 0, s, a);
     return hipGetLastError();
+}
+
+template <int NB>
+hipError_t helmert_v(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s) {
+    switch (variant) {
+        case 1: return helmert_nb<NB, 1>(a, unit, fuse, s);
+        case 2: return helmert_nb<NB, 2>(a, unit, fuse, s);
+        default: return helmert_nb<NB, 0>(a, unit, fuse, s);
+    }
+}
+
+template <int NB>
+hipError_t dense_v(const DenseArgs &a, int variant, hipStream_t s) {
+    switch (variant) {
+        case 1: return dense_nb<NB, 1>(a, s);
+        case 2: return dense_nb<NB, 2>(a, s);
+        default: return dense_nb<NB, 0>(a, s);
+    }
 }
 
 }  // namespace
 
-int tile_items_for(int ncols, int variant) {
-    const bool v1 = variant == 1;
+int tile_items_for(int ncols, int) {
     switch (nb_for(ncols)) {
-        case 8: return 64 * (v1 ? Shape<8, 1>::RPL : Shape<8, 0>::RPL);
-        case 16: return 64 * (v1 ? Shape<16, 1>::RPL : Shape<16, 0>::RPL);
-        case 32: return 64 * (v1 ? Shape<32, 1>::RPL : Shape<32, 0>::RPL);
-        default: return 64 * (v1 ? Shape<64, 1>::RPL : Shape<64, 0>::RPL);
+        case 8: return 64 * Shape<8, 0>::RPL;
+        case 16: return 64 * Shape<16, 0>::RPL;
+        case 32: return 64 * Shape<32, 0>::RPL;
+        default: return 64 * Shape<64, 0>::RPL;
     }
 }
 
 int dense_tile_rows_for(int ncols) { return tile_items_for(ncols, 0); }
 int waves_per_block() { return kWavesPerBlock; }
+int num_variants() { return kVariants; }
 
 hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s) {
     if (a.waves <= 0 || a.nchunks <= 0) return hipSuccess;
-    const bool v1 = variant == 1;
     switch (nb_for(a.ncols)) {
-        case 8: return v1 ? helmert_nb<8, 1>(a, unit, fuse, s) : helmert_nb<8, 0>(a, unit, fuse, s);
-        case 16: return v1 ? helmert_nb<16, 1>(a, unit, fuse, s) : helmert_nb<16, 0>(a, unit, fuse, s);
-        case 32: return v1 ? helmert_nb<32, 1>(a, unit, fuse, s) : helmert_nb<32, 0>(a, unit, fuse, s);
+        case 8: return helmert_v<8>(a, unit, fuse, variant, s);
+        case 16: return helmert_v<16>(a, unit, fuse, variant, s);
+        case 32: return helmert_v<32>(a, unit, fuse, variant, s);
         default: return helmert_nb<64, 0>(a, unit, fuse, s);
     }
 }
 
 hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
     if (a.waves <= 0) return hipSuccess;
-    const bool v1 = variant == 1;
     switch (nb_for(a.n)) {
-        case 8: return v1 ? dense_nb<8, 1>(a, s) : dense_nb<8, 0>(a, s);
-        case 16: return v1 ? dense_nb<16, 1>(a, s) : dense_nb<16, 0>(a, s);
-        case 32: return v1 ? dense_nb<32, 1>(a, s) : dense_nb<32, 0>(a, s);
+        case 8: return dense_v<8>(a, variant, s);
+        case 16: return dense_v<16>(a, variant, s);
+        case 32: return dense_v<32>(a, variant, s);
         default: return dense_nb<64, 0>(a, s);
     }
 }

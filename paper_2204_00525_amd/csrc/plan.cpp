@@ -257,7 +257,8 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     const bool keys_on_host = opts && opts->keys_on_host;
     p->analyze_only = opts && opts->analyze_only;
     p->variant = opts ? opts->variant : 0;
-    if (p->variant < 0 || p->variant > 1) return set_error(p, FIGARO_EINVAL, "variant must be 0 or 1");
+    if (p->variant < 0 || p->variant >= num_variants())
+        return set_error(p, FIGARO_EINVAL, "variant out of range");
     if (p->tile_items < 0) return set_error(p, FIGARO_EINVAL, "tile_items must be >= 0");
     // ---- argument checks
     int roots = 0;

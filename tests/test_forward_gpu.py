@@ -236,10 +236,12 @@ def test_counts_match_definitions(F, oracle_lib, maker):
 
 
 @pytest.mark.parametrize("name", ["config1", "config2_div1000", "config3_div1000", "two_rel_zipf", "chain4_zipf",
-                                  "star_nonpk"])
+                                  "star_nonpk", "paper_fig3_b", "star_dim_root"])
 @pytest.mark.parametrize("tile", [0, 64])
-def test_forward_variant1(F, oracle_lib, name, tile):
-    """The alternative tile shape (two waves per SIMD) gives the same R."""
+@pytest.mark.parametrize("variant", [1, 2])
+def test_forward_variants(F, oracle_lib, name, tile, variant):
+    """The other forms of the register-tile QR (compact column loop; two
+    waves per SIMD) give the same R."""
     inst = CASES[name]()
-    R, plan, _ = gpu_r(F, inst, variant=1, tile_items=tile)
+    R, plan, _ = gpu_r(F, inst, variant=variant, tile_items=tile)
     assert _relf(R, oracle_lib.r_of_join(inst)) <= TOL
