@@ -19,6 +19,22 @@ int64_t figaro_debug_stack_rows(figaro_plan_t plan);
 figaro_status figaro_debug_stack(figaro_plan_t plan, const double *const *values, const int64_t *ld,
                                  double *host_out, hipStream_t stream);
 
+/* Rows per register tile of one wave of the dense TSQR kernel for n columns
+ * and a kernel variant (as in figaro_plan_options), or -1 if out of range. */
+int64_t figaro_debug_tile_rows(int32_t n, int32_t variant);
+
+/* One launch of the dense TSQR step (section "Post-processing") on a plain
+ * matrix: `in` is a device column-major rows x n matrix (ld_in >= rows);
+ * workgroup b folds rows [b*W, (b+1)*W), W = 4 * tiles_per_wave *
+ * figaro_debug_tile_rows(n, variant), into one n x n R.  With workgroups ==
+ * 1 and final_r != NULL the sign-normalised R is written to final_r (n x n,
+ * column-major); otherwise workgroup b writes its R to rows b*n..b*n+n-1 of
+ * `out` (column-major, ld_out >= workgroups * n).  FIGARO_EINVAL when the
+ * workgroups do not cover the rows or an argument is out of range. */
+figaro_status figaro_debug_dense_step(int32_t n, int64_t rows, const double *in, int64_t ld_in,
+                                      int32_t workgroups, int64_t tiles_per_wave, int32_t variant,
+                                      double *out, int64_t ld_out, double *final_r, hipStream_t stream);
+
 /* Layout of the stack: up to max_regions triples (block id, first row, rows)
  * written to regions_host; returns the number of regions. */
 int32_t figaro_debug_stack_layout(figaro_plan_t plan, int64_t *regions_host, int32_t max_regions);

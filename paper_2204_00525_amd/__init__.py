@@ -85,6 +85,8 @@ def lib():
         "figaro_debug_stack_rows": (i64, [vp]),
         "figaro_debug_stack": (i32, [vp, pp, pi64, vp, vp]),
         "figaro_debug_stack_layout": (i32, [vp, pi64, i32]),
+        "figaro_debug_tile_rows": (i64, [i32, i32]),
+        "figaro_debug_dense_step": (i32, [i32, i64, vp, i64, i32, i64, i32, vp, i64, vp, vp]),
     }
     optional = {
         "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, pi64, vp]),
@@ -425,3 +427,28 @@ def device_values(plan: Plan, inst, device="cuda") -> List:
         v = torch.as_tensor(np.ascontiguousarray(rel.values, dtype=np.float64)).to(device)
         out.append(plan.to_plan_order(i, v))
     return out
+
+
+def debug_tile_rows(n: int, variant: int = 0) -> int:
+    """Rows per register tile of one wave of the dense TSQR kernel."""
+    return int(lib().figaro_debug_tile_rows(n, variant))
+
+
+def debug_dense_step(A, workgroups: int, tiles_per_wave: int, variant: int = 0, stream=None):
+    """One launch of the dense TSQR kernel on a device FP64 matrix A (rows x
+    n, column-major, i.e. A.T contiguous).  Returns the n x n sign-normalised
+    R for one workgroup, else the (workgroups*n) x n stack of per-workgroup R."""
+    import torch
+    rows, n = A.shape
+    At = A.t().contiguous() if not A.t().is_contiguous() else A.t()
+    if workgroups == 1:
+        R = torch.zeros((n, n), dtype=torch.float64, device=A.device)
+        _check(lib().figaro_debug_dense_step(n, rows, ctypes.c_void_p(At.data_ptr()), max(rows, 1), 1,
+                                             tiles_per_wave, variant, None, 0, ctypes.c_void_p(R.data_ptr()),
+                                             _stream_handle(stream)), None)
+        return R.t()
+    out = torch.zeros((n, workgroups * n), dtype=torch.float64, device=A.device)
+    _check(lib().figaro_debug_dense_step(n, rows, ctypes.c_void_p(At.data_ptr()), max(rows, 1), workgroups,
+                                         tiles_per_wave, variant, ctypes.c_void_p(out.data_ptr()), workgroups * n,
+                                         None, _stream_handle(stream)), None)
+    return out.t()

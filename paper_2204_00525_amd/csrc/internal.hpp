@@ -125,6 +125,8 @@ struct JoinArgs {
     const int32_t *colpos[kMaxChildren];
     const int32_t *cidx[kMaxChildren];
     const double *mult[kMaxChildren];
+    int8_t col_src[kMaxCols];    // per output column: -1 own, else the child
+    int8_t col_idx[kMaxCols];    // per output column: column within its source
 };
 
 // Root emit: rows s[.][g] / sqrt(c_g) into the stack (or R0).
@@ -198,7 +200,7 @@ hipError_t launch_copy_cols(const double *src, int64_t ld_src, double *dst, int6
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 int tile_items_for(int ncols, int variant);   // items per chunk of the register-tile kernel
 int num_variants();                           // number of register-tile kernel variants
-int dense_tile_rows_for(int ncols);   // rows per tile of the dense kernel
+int dense_tile_rows_for(int ncols, int variant);   // rows per tile of the dense kernel
 int waves_per_block();                // waves per workgroup of the QR kernels
 
 // ---------------------------------------------------------------------------
@@ -263,6 +265,8 @@ struct RelPlan {
     std::vector<int32_t *> d_cidx;
     std::vector<double *> d_mult;
     std::vector<int32_t *> d_colpos;
+    int8_t col_src[kMaxCols] = {};   // per subtree column: -1 own, else child index
+    int8_t col_idx[kMaxCols] = {};   // per subtree column: column within its source
     double *d_s = nullptr;           // [nsub][G]
     double *d_gs = nullptr;          // gradient of s, [nsub][G]
     std::vector<int64_t *> d_inv_off;   // per child: [P_child+1]

@@ -173,15 +173,17 @@ __device__ __forceinline__ void qr_columns(double (&x)[RPL][NB], double *rw, std
     (qr_column<NB, RPL, Js>(x, rw), ...);
 }
 
-// Same step for wide tiles with a runtime column loop: the pivot column is
-// always register column 0 and every step rotates the columns left by one, so
-// after NB steps every column is back in place.  At step j register column k
-// holds column j + k (mod NB); the columns that wrap around are already
-// eliminated (zero in X and below the diagonal of R), so their update is
-// the identity.
+// Same step for wide tiles with a runtime column loop over the `ncols` live
+// columns: the pivot column is always register column 0 and every step
+// rotates the register columns left by one, so at step j register column k
+// holds column j + k.  Register columns that wrap around hold eliminated
+// (zero) columns, and their updates are the identity; their R entries go to
+// a spare row at the end of the slice, which keeps the step branch-free.
+// The columns of the tile end up rotated, which is harmless: the tile is
+// discarded and R lives in LDS in its own column order.
 template <int NB, int RPL>
-__device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *rw) {
-    for (int j = 0; j < NB; ++j) {
+__device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *rw, int ncols) {
+    for (int j = 0; j < ncols; ++j) {
         double d[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -192,7 +194,11 @@ __device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *
         }
         double p[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) p[k] = (k < NB - j) ? rw[j * NB + j + k] : 0.0;
+        for (int k = 0; k < NB; ++k) {
+            const bool live = k < NB - j;
+            const double v = rw[live ? j * NB + j + k : NB * NB + k];
+            p[k] = live ? v : 0.0;
+        }
         wave_sum_batch<NB>(d);
         const Reflector h = reflector(p[0], d[0]);
 #pragma unroll
@@ -201,7 +207,7 @@ __device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *
             const double g = h.ts * w;
 #pragma unroll
             for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][0], x[r][k]);
-            if (k < NB - j) rw[j * NB + j + k] = fma(-h.tau, w, p[k]);
+            rw[(k < NB - j) ? j * NB + j + k : NB * NB + k] = fma(-h.tau, w, p[k]);
         }
         rw[j * NB + j] = h.rjj;
         // rotate columns left by one (column j is zero now)
@@ -215,35 +221,37 @@ __device__ __forceinline__ void qr_accumulate_rot(double (&x)[RPL][NB], double *
 }
 
 // ROT selects the compact runtime-loop form (code size O(NB) instead of
-// O(NB^2), at twice the arithmetic); wide tiles always use it.
+// O(NB^2)); the widest tiles always use it.
 template <int NB, int RPL, bool ROT = false>
-__device__ __forceinline__ void qr_step(double (&x)[RPL][NB], double *rw) {
-    if constexpr (NB <= 32 && !ROT) qr_columns<NB, RPL>(x, rw, std::make_integer_sequence<int, NB>{});
-    else qr_accumulate_rot<NB, RPL>(x, rw);
+__device__ __forceinline__ void qr_step(double (&x)[RPL][NB], double *rw, int ncols) {
+    if constexpr (NB <= 40 && !ROT) qr_columns<NB, RPL>(x, rw, std::make_integer_sequence<int, NB>{});
+    else qr_accumulate_rot<NB, RPL>(x, rw, ncols);
 }
 
 // Each wave keeps its running R in its own LDS slice (NB x NB doubles,
-// row-major, zero below the diagonal).  Merging the waves of a workgroup:
-// after a barrier, wave 0 folds the R factors of waves 1..3 in as extra
-// tiles through the same QR call site as the data tiles.
-template <int NB>
+// row-major, zero below the diagonal; the compact form adds a spare row).
+// Merging the waves of a workgroup: after a barrier, wave 0 folds the R
+// factors of waves 1..3 in as extra tiles through the same QR call site as
+// the data tiles.
+template <int NB, bool ROT>
 constexpr int r_slice_doubles() {
-    return NB * NB;
+    return NB * NB + (ROT ? NB : 0);
 }
 
-template <int NB>
+template <int NB, bool ROT>
 __device__ __forceinline__ void r_zero(double *rw, int lane) {
-    for (int i = lane; i < NB * NB; i += 64) rw[i] = 0.0;
+    for (int i = lane; i < r_slice_doubles<NB, ROT>(); i += 64) rw[i] = 0.0;
 }
 
-template <int NB, int RPL>
+template <int NB, int RPL, bool ROT>
 __device__ __forceinline__ void merge_load(double (&x)[RPL][NB], int lane, int t0, const double *lds) {
     constexpr int ROWS = (kWavesPerBlock - 1) * NB;
+    constexpr int SL = r_slice_doubles<NB, ROT>();
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
         const int r = t0 + lane * RPL + k;
-        // row r of the merge block: row (r % NB) of wave 1 + r / NB
-        const int src = (r < ROWS) ? (NB * NB + r * NB) : 0;
+        // row r of the merge block: row r % NB of wave 1 + r / NB
+        const int src = (r < ROWS) ? ((1 + r / NB) * SL + (r % NB) * NB) : 0;
 #pragma unroll
         for (int c = 0; c < NB; ++c) x[k][c] = (r < ROWS) ? lds[src + c] : 0.0;
     }
@@ -279,7 +287,7 @@ __device__ __forceinline__ void store_r(const HelmertArgs &a, const double *rw, 
 // one barrier and all branches around it are uniform within a wave.
 template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
-    __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB>() : 1];
+    __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB, ROT>() : 1];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int wave = blockIdx.x * kWavesPerBlock + wib;
@@ -287,8 +295,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     if (!FUSE && !active) return;
     const int64_t c_begin = active ? a.nchunks * wave / a.waves : 0;
     const int64_t c_end = active ? a.nchunks * (wave + 1) / a.waves : 0;
-    double *rw = lds + (FUSE ? wib * r_slice_doubles<NB>() : 0);
-    if constexpr (FUSE) r_zero<NB>(rw, lane);
+    double *rw = lds + (FUSE ? wib * r_slice_doubles<NB, ROT>() : 0);
+    if constexpr (FUSE) r_zero<NB, ROT>(rw, lane);
     const int64_t n_data = c_end - c_begin;
     const int64_t n_iter = n_data + ((FUSE && wib == 0) ? merge_tiles<NB, RPL>() : 0);
 
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
         double x[RPL][NB];
         if (FUSE && it >= n_data) {
             if (it == n_data) __syncthreads();
-            merge_load<NB, RPL>(x, lane, (int)(it - n_data) * 64 * RPL, lds);
+            merge_load<NB, RPL, ROT>(x, lane, (int)(it - n_data) * 64 * RPL, lds);
         } else {
             const int64_t ch = c_begin + it;
             const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
@@ -391,7 +399,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                 continue;
             }
         }
-        if constexpr (FUSE) qr_step<NB, RPL, ROT>(x, rw);
+        if constexpr (FUSE) qr_step<NB, RPL, ROT>(x, rw, a.ncols);
     }
     if constexpr (FUSE) {
         if (wib > 0) __syncthreads();
@@ -405,20 +413,20 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
 // Same merge protocol as k_helmert.
 template <int NB, int RPL, bool ROT, int OCC>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a) {
-    __shared__ double lds[kWavesPerBlock * r_slice_doubles<NB>()];
+    __shared__ double lds[kWavesPerBlock * r_slice_doubles<NB, ROT>()];
     const int lane = threadIdx.x & 63;
     const int wib = threadIdx.x >> 6;
     const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wib;
     constexpr int T = 64 * RPL;
-    double *rw = lds + wib * r_slice_doubles<NB>();
-    r_zero<NB>(rw, lane);
+    double *rw = lds + wib * r_slice_doubles<NB, ROT>();
+    r_zero<NB, ROT>(rw, lane);
     const int64_t n_data = a.tiles_per_wave;
     const int64_t n_iter = n_data + ((wib == 0) ? merge_tiles<NB, RPL>() : 0);
     for (int64_t it = 0; it < n_iter; ++it) {
         double x[RPL][NB];
         if (it >= n_data) {
             if (it == n_data) __syncthreads();
-            merge_load<NB, RPL>(x, lane, (int)(it - n_data) * T, lds);
+            merge_load<NB, RPL, ROT>(x, lane, (int)(it - n_data) * T, lds);
         } else {
             const int64_t base = (wave * a.tiles_per_wave + it) * T + (int64_t)lane * RPL;
 #pragma unroll
@@ -429,7 +437,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
                 for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? col[base + k] : 0.0;
             }
         }
-        qr_step<NB, RPL, ROT>(x, rw);
+        qr_step<NB, RPL, ROT>(x, rw, a.n);
     }
     if (wib > 0) {
         __syncthreads();
@@ -449,29 +457,33 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
     }
 }
 
+// One thread per (key group, output column): the column's source (own sums
+// or a child's sums gathered through the child index) times the exact
+// integer multiplier of the group.
 __global__ void k_join(JoinArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int oc = blockIdx.y;
     if (g >= a.groups) return;
-    const double om = a.own_mult[g];
-    for (int c = 0; c < a.own_cols; ++c)
-        a.s[(int64_t)(a.own_pos + c) * a.ld_s + g] = a.own[(int64_t)c * a.ld_own + g] * om;
-    for (int j = 0; j < a.nchildren; ++j) {
-        const int64_t q = a.cidx[j][g];
-        const double m = a.mult[j][g];
-        const double *sg = a.sigma[j];
-        const int64_t ld = a.ld_sigma[j];
-        const int32_t *pos = a.colpos[j];
-        for (int c = 0; c < a.child_cols[j]; ++c) a.s[(int64_t)pos[c] * a.ld_s + g] = sg[(int64_t)c * ld + q] * m;
+    const int src = a.col_src[oc], c = a.col_idx[oc];
+    double v;
+    if (src < 0) {
+        v = a.own[(int64_t)c * a.ld_own + g] * a.own_mult[g];
+    } else {
+        const int64_t q = a.cidx[src][g];
+        v = a.sigma[src][(int64_t)c * a.ld_sigma[src] + q] * a.mult[src][g];
     }
+    a.s[(int64_t)oc * a.ld_s + g] = v;
 }
 
+// One thread per (root key group, column).
 __global__ void k_root(RootArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
     if (g >= a.groups) return;
     const double f = a.inv_sqrt_c ? a.inv_sqrt_c[g] : 1.0;
     const int64_t row = a.row0 + g;
-    for (int c = 0; c < a.n; ++c) a.dst[(int64_t)c * a.ld_dst + row] = a.s[(int64_t)c * a.ld_s + g] * f;
-    if (a.block_of_row) a.block_of_row[row] = a.block_id;
+    a.dst[(int64_t)c * a.ld_dst + row] = a.s[(int64_t)c * a.ld_s + g] * f;
+    if (c == 0 && a.block_of_row) a.block_of_row[row] = a.block_id;
 }
 
 __global__ void k_permute(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, const int64_t *perm,
@@ -502,6 +514,7 @@ int nb_for(int ncols) {
     if (ncols <= 8) return 8;
     if (ncols <= 16) return 16;
     if (ncols <= 32) return 32;
+    if (ncols <= 40) return 40;
     return 64;
 }
 
@@ -512,9 +525,10 @@ int nb_for(int ncols) {
 // unrolled, two waves per SIMD.
 template <int NB, int V>
 struct Shape {
-    static constexpr int RPL = NB <= 8 ? 8 : NB <= 16 ? 4 : NB <= 32 ? 2 : 1;
+    static constexpr bool ROT = V == 1 || NB > 40;
+    static constexpr int RPL = V == 2 ? (NB <= 8 ? 6 : NB <= 16 ? 3 : 1)
+                                      : (NB <= 8 ? 8 : NB <= 16 ? 4 : (NB <= 40 && !ROT) ? 2 : 1);
     static constexpr int OCC = (V == 2 && NB <= 32) ? 2 : 1;
-    static constexpr bool ROT = V == 1 || NB > 32;
 };
 
 constexpr int kVariants = 3;
@@ -562,16 +576,26 @@ hipError_t dense_v(const DenseArgs &a, int variant, hipStream_t s) {
 
 }  // namespace
 
-int tile_items_for(int ncols, int) {
+template <int V>
+int tile_items_v(int ncols) {
     switch (nb_for(ncols)) {
-        case 8: return 64 * Shape<8, 0>::RPL;
-        case 16: return 64 * Shape<16, 0>::RPL;
-        case 32: return 64 * Shape<32, 0>::RPL;
+        case 8: return 64 * Shape<8, V>::RPL;
+        case 16: return 64 * Shape<16, V>::RPL;
+        case 32: return 64 * Shape<32, V>::RPL;
+        case 40: return 64 * (V == 1 ? Shape<40, 1>::RPL : Shape<40, 0>::RPL);
         default: return 64 * Shape<64, 0>::RPL;
     }
 }
 
-int dense_tile_rows_for(int ncols) { return tile_items_for(ncols, 0); }
+int tile_items_for(int ncols, int variant) {
+    switch (variant) {
+        case 1: return tile_items_v<1>(ncols);
+        case 2: return tile_items_v<2>(ncols);
+        default: return tile_items_v<0>(ncols);
+    }
+}
+
+int dense_tile_rows_for(int ncols, int variant) { return tile_items_for(ncols, variant); }
 int waves_per_block() { return kWavesPerBlock; }
 int num_variants() { return kVariants; }
 
@@ -581,6 +605,7 @@ hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int varian
         case 8: return helmert_v<8>(a, unit, fuse, variant, s);
         case 16: return helmert_v<16>(a, unit, fuse, variant, s);
         case 32: return helmert_v<32>(a, unit, fuse, variant, s);
+        case 40: return variant == 1 ? helmert_nb<40, 1>(a, unit, fuse, s) : helmert_nb<40, 0>(a, unit, fuse, s);
         default: return helmert_nb<64, 0>(a, unit, fuse, s);
     }
 }
@@ -591,21 +616,22 @@ hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
         case 8: return dense_v<8>(a, variant, s);
         case 16: return dense_v<16>(a, variant, s);
         case 32: return dense_v<32>(a, variant, s);
+        case 40: return variant == 1 ? dense_nb<40, 1>(a, s) : dense_nb<40, 0>(a, s);
         default: return dense_nb<64, 0>(a, s);
     }
 }
 
 hipError_t launch_join(const JoinArgs &a, hipStream_t s) {
-    if (a.groups <= 0) return hipSuccess;
+    if (a.groups <= 0 || a.nsub <= 0) return hipSuccess;
     const int bs = 256;
-    hipLaunchKernelGGL(k_join, dim3((unsigned)((a.groups + bs - 1) / bs)), dim3(bs), 0, s, a);
+    hipLaunchKernelGGL(k_join, dim3((unsigned)((a.groups + bs - 1) / bs), (unsigned)a.nsub), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_root(const RootArgs &a, bool, hipStream_t s) {
-    if (a.groups <= 0) return hipSuccess;
+    if (a.groups <= 0 || a.n <= 0) return hipSuccess;
     const int bs = 256;
-    hipLaunchKernelGGL(k_root, dim3((unsigned)((a.groups + bs - 1) / bs)), dim3(bs), 0, s, a);
+    hipLaunchKernelGGL(k_root, dim3((unsigned)((a.groups + bs - 1) / bs), (unsigned)a.n), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

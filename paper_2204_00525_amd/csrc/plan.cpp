@@ -592,6 +592,10 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             if ((st = finish_task(p, R.a2, n)) != FIGARO_OK) return st;
         }
         if (!R.children.empty()) {
+            for (int c = 0; c < R.ncols; ++c) {
+                R.col_src[R.own_pos + c] = -1;
+                R.col_idx[R.own_pos + c] = (int8_t)c;
+            }
             std::vector<double> own(R.G);
             std::vector<std::vector<double>> mult(R.children.size(), std::vector<double>(R.G));
             for (int64_t g = 0; g < R.G; ++g) {
@@ -618,6 +622,10 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
                     pos.push_back((int32_t)(std::lower_bound(R.sub_cols.begin(), R.sub_cols.end(), col) -
                                             R.sub_cols.begin()));
                 if (dev_upload(p, &dp, pos) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                for (size_t q = 0; q < pos.size(); ++q) {
+                    R.col_src[pos[q]] = (int8_t)c;
+                    R.col_idx[pos[q]] = (int8_t)q;
+                }
                 R.d_cidx.push_back(di);
                 R.d_mult.push_back(dm);
                 R.d_colpos.push_back(dp);
@@ -693,7 +701,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     p->r0_rows = r0row;
     // dense TSQR levels over the stack: a workgroup (waves_per_block waves)
     // folds waves_per_block * tiles_per_wave tiles into one R of n rows
-    const int64_t dt = dense_tile_rows_for(n);
+    const int64_t dt = dense_tile_rows_for(n, p->variant);
     const int64_t wpb = waves_per_block();
     int64_t rows = srow;
     int64_t maxnext = 0;

@@ -150,6 +150,10 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
             j.own_pos = Rl.own_pos;
             j.own_mult = Rl.d_own_mult;
             j.nchildren = (int32_t)Rl.children.size();
+            for (int c = 0; c < Rl.nsub; ++c) {
+                j.col_src[c] = Rl.col_src[c];
+                j.col_idx[c] = Rl.col_idx[c];
+            }
             for (size_t c = 0; c < Rl.children.size(); ++c) {
                 int ch = Rl.children[c];
                 j.sigma[c] = B.sigma[ch];
@@ -413,6 +417,35 @@ figaro_status figaro_unpermute_values(figaro_plan_t p, int32_t rel, const double
 }
 
 int64_t figaro_debug_stack_rows(figaro_plan_t p) { return p ? p->stack_rows : -1; }
+
+int64_t figaro_debug_tile_rows(int32_t n, int32_t variant) {
+    if (n < 1 || n > kMaxCols || variant < 0 || variant >= num_variants()) return -1;
+    return dense_tile_rows_for(n, variant);
+}
+
+figaro_status figaro_debug_dense_step(int32_t n, int64_t rows, const double *in, int64_t ld_in, int32_t workgroups,
+                                      int64_t tiles_per_wave, int32_t variant, double *out, int64_t ld_out,
+                                      double *final_r, hipStream_t stream) {
+    if (n < 1 || n > kMaxCols || rows < 0 || !in || ld_in < rows || workgroups < 1 || tiles_per_wave < 1 ||
+        variant < 0 || variant >= num_variants())
+        return set_error(nullptr, FIGARO_EINVAL, "bad argument");
+    const int64_t per_wg = (int64_t)waves_per_block() * tiles_per_wave * dense_tile_rows_for(n, variant);
+    if ((int64_t)workgroups * per_wg < rows) return set_error(nullptr, FIGARO_EINVAL, "workgroups do not cover the rows");
+    const bool fin = workgroups == 1 && final_r;
+    if (!fin && (!out || ld_out < (int64_t)workgroups * n)) return set_error(nullptr, FIGARO_EINVAL, "bad output");
+    DenseArgs a{};
+    a.in = in;
+    a.ld_in = ld_in;
+    a.rows = rows;
+    a.n = n;
+    a.out = out;
+    a.ld_out = ld_out;
+    a.waves = workgroups;
+    a.tiles_per_wave = tiles_per_wave;
+    a.final_r = fin ? final_r : nullptr;
+    hipError_t e = launch_dense(a, variant, stream);
+    return e == hipSuccess ? FIGARO_OK : set_error(nullptr, FIGARO_EHIP, hipGetErrorString(e));
+}
 
 int32_t figaro_debug_stack_layout(figaro_plan_t p, int64_t *out, int32_t max_regions) {
     if (!p || !out) return -1;

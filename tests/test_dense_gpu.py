@@ -1,0 +1,72 @@
+"""The dense TSQR step (section "Post-processing") on plain matrices, against
+the oracle's textbook Householder QR (needs an MI355X)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_00525_amd as F
+    F.lib()
+    return F
+
+
+def _relf(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("n", [1, 5, 8, 13, 16, 24, 32, 40, 64])
+def test_single_workgroup_matches_householder(F, oracle_lib, n, variant):
+    import torch
+    tile = F.debug_tile_rows(n, variant)
+    tpw = 2
+    rows = 4 * tpw * tile - 37          # several tiles and a ragged tail
+    rng = np.random.default_rng(100 + n)
+    A = rng.standard_normal((rows, n)) * 10.0 ** rng.uniform(-3, 3, n)
+    R = F.debug_dense_step(torch.as_tensor(A).cuda(), 1, tpw, variant).cpu().numpy()
+    ref, _ = oracle_lib.householder_r(np.asfortranarray(A))
+    assert np.allclose(np.tril(R, -1), 0.0)
+    assert np.all(np.diag(R) >= 0)
+    assert _relf(R, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [7, 16, 32, 48])
+def test_many_workgroups_preserve_gram(F, oracle_lib, n):
+    import torch
+    tile = F.debug_tile_rows(n, 0)
+    wg = 9
+    rows = wg * 4 * tile - 5
+    rng = np.random.default_rng(7 + n)
+    A = rng.standard_normal((rows, n))
+    S = F.debug_dense_step(torch.as_tensor(A).cuda(), wg, 1, 0).cpu().numpy()
+    assert S.shape == (wg * n, n)
+    for b in range(wg):
+        assert np.allclose(np.tril(S[b * n:(b + 1) * n], -1), 0.0)
+    Ghi, Glo = oracle_lib.gram_ld(np.asfortranarray(A))
+    assert _relf(S.T @ S, Ghi + Glo) <= 1e-13
+
+
+def test_rank_deficient_and_zero_columns(F, oracle_lib):
+    import torch
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((300, 10))
+    A[:, 3] = 0.0
+    A[:, 7] = 2.0 * A[:, 1]
+    R = F.debug_dense_step(torch.as_tensor(A).cuda(), 1, 2, 0).cpu().numpy()
+    assert np.all(np.isfinite(R))
+    Ghi, Glo = oracle_lib.gram_ld(np.asfortranarray(A))
+    assert _relf(R.T @ R, Ghi + Glo) <= 1e-13
+
+
+def test_coverage_is_checked(F):
+    import torch
+    tile = F.debug_tile_rows(16, 0)
+    A = torch.zeros((4 * tile + 1, 16), dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FigaroError):
+        F.debug_dense_step(A, 1, 1, 0)
