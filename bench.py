@@ -1,22 +1,32 @@
-"""Benchmark: tuples/s to R (FP64) of a two-relation join on one MI355X.
+"""Benchmark: tuples/s to R (FP64) of an acyclic join on one MI355X.
 
-Workload: S(a, 16 FP64 cols) join T(a, 16 FP64 cols), 2,000,000 tuples each,
-join key Zipf(1.1) over 1000 ids (about 1.9e11 join rows, never
-materialised), seeded synthetic data.  A step is one full forward pass
-(every kernel from the relation values to R) on inputs already resident in
-HBM in plan order; the plan (keys only) is built once before timing, like the
-paper's exclusion of sort time.
+Headline workload (the `value` of the JSON line): S(a, 16 FP64 cols) join
+T(a, 16 FP64 cols), 2,000,000 tuples each, join key Zipf(1.1) over 1000 ids
+(about 1.9e11 join rows, never materialised), seeded synthetic data.  A step
+is one full forward pass (every kernel from the relation values to R) on
+inputs already resident in HBM in plan order; the plan (keys only) is built
+once before timing, like the paper's exclusion of sort time, and its time is
+reported separately.
 
-Prints one JSON line with the metric, the roofline of the dominant kernel
-(from HIP events recorded by the library around each launch, on the stream
-the kernels run on), the CPU oracle timed on a bounded sample of the same
-workload, and a comparator: QR of the materialised join on the GPU
-(torch.linalg.qr, FP64) on a subsample small enough to materialise, next to
-this library on the same subsample.
+Also reported on the same line:
+  * fwd_bwd: forward + hand-written backward of the loss
+    L(R) = R_nn^2 / 2 + sum_i log R_ii on the same workload;
+  * star: the key/foreign-key star join (fact table 10^7 rows with 4 foreign
+    keys into four 10^5-row dimensions, 8 columns each, n = 40), forward and
+    forward + backward of the same loss, next to torch.linalg.qr of its
+    materialised join (10^7 x 40) on the GPU;
+  * roofline: the dominant kernel, timed by HIP events that the library
+    records around each launch on the stream it launches on; `traffic` is the
+    calibrated HBM byte count from rocprofv3 counters stored under profiles/,
+    or null when the kernel source changed since they were taken;
+  * cpu_baseline: the CPU oracle timed on a bounded sample;
+  * comparator: torch.linalg.qr of the materialised two-relation join on a
+    subsample small enough to materialise, next to this library on it.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,11 +38,42 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_heads_tails_two_relation_2x2M.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2204_00525_amd", "csrc", f)
+                  for f in ("kernels.hip", "device_common.hpp", "internal.hpp")]
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def loss_grad(R):
+    """dL/dR for L(R) = R_nn^2 / 2 + sum_i log R_ii."""
+    import torch
+    d = torch.diagonal(R)
+    dR = torch.diag(1.0 / d)
+    dR[-1, -1] += R[-1, -1]
+    return dR
+
+
+def time_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
 
 
 def time_forward(plan, vals, steps, warmup, profile=False):
@@ -54,9 +95,15 @@ def time_forward(plan, vals, steps, warmup, profile=False):
     return (t1 - t0) / steps, R, prof
 
 
+def fwd_bwd_step(plan, vals):
+    R = plan.r_factor(vals)
+    return plan.r_backward(vals, R, loss_grad(R))
+
+
 def cpu_baseline(div: int):
-    """The oracle (materialise + textbook Householder, one thread) on the
-    config-2 shape divided by `div`."""
+    """The oracle (index nested-loop join + textbook Householder, one
+    thread) on the two-relation workload with every relation divided by
+    `div`."""
     import oracle
     import synth
     oracle.build()
@@ -68,9 +115,23 @@ def cpu_baseline(div: int):
     return inst.M / (t1 - t0), t1 - t0, inst.M, A.shape[0]
 
 
+def materialized_qr_ms(A, reps=3):
+    import torch
+    for _ in range(1):
+        Rq = torch.linalg.qr(A, mode="r")[1]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        Rq = torch.linalg.qr(A, mode="r")[1]
+    torch.cuda.synchronize()
+    Rq = Rq * torch.sign(torch.diagonal(Rq))[:, None]
+    return (time.perf_counter() - t0) / reps * 1e3, Rq
+
+
 def comparator(F, div: int):
-    """torch.linalg.qr (FP64, GPU) of the materialised join vs this library,
-    both on the config-2 shape divided by `div`."""
+    """torch.linalg.qr (FP64, GPU) of the materialised two-relation join vs
+    this library, both on the workload divided by `div`, both against the
+    oracle."""
     import torch
     import oracle
     import synth
@@ -79,27 +140,81 @@ def comparator(F, div: int):
     vals = F.device_values(plan, inst)
     t_fig, R, _ = time_forward(plan, vals, 10, 3)
     t0 = time.perf_counter()
-    A = torch.as_tensor(np.ascontiguousarray(oracle.join(inst))).cuda()
+    Ah = oracle.join(inst)
+    A = torch.as_tensor(np.ascontiguousarray(Ah)).cuda()
     torch.cuda.synchronize()
     t_mat = time.perf_counter() - t0
-    for _ in range(2):
-        Rq = torch.linalg.qr(A, mode="r")[1]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 3
-    for _ in range(reps):
-        Rq = torch.linalg.qr(A, mode="r")[1]
-    torch.cuda.synchronize()
-    t_qr = (time.perf_counter() - t0) / reps
-    Rq = Rq * torch.sign(torch.diagonal(Rq))[:, None]
-    Rr, _ = oracle.householder_r(oracle.join(inst))
+    t_qr, Rq = materialized_qr_ms(A)
+    Rr, _ = oracle.householder_r(Ah)
     err_fig = float(np.linalg.norm(R.cpu().numpy() - Rr) / np.linalg.norm(Rr))
     err_qr = float(np.linalg.norm(Rq.cpu().numpy() - Rr) / np.linalg.norm(Rr))
-    return {"workload": f"config-2 shape / {div}: 2 x {inst.rels[0].rows} tuples, "
+    return {"workload": f"two-relation join / {div}: 2 x {inst.rels[0].rows} tuples, "
                         f"{A.shape[0]} join rows x {A.shape[1]}",
-            "figaro_ms": t_fig * 1e3, "materialized_qr_ms": t_qr * 1e3,
-            "materialize_host_ms": t_mat * 1e3, "speedup": t_qr / t_fig,
-            "figaro_rel_err": err_fig, "materialized_qr_rel_err": err_qr}
+            "figaro_ms": t_fig * 1e3, "materialized_qr_ms": t_qr,
+            "materialize_host_ms": t_mat * 1e3, "speedup": t_qr / (t_fig * 1e3),
+            "figaro_rel_err": err_fig, "materialized_qr_rel_err": err_qr,
+            "reference": "CPU oracle (materialised join, textbook Householder)"}
+
+
+def star(F, steps, warmup, with_comparator):
+    """Key/foreign-key star join: forward, forward+backward, comparator."""
+    import torch
+    import oracle
+    import synth
+    log("star join: generating inputs")
+    inst = synth.config3()
+    t0 = time.perf_counter()
+    plan = F.plan_from_instance(inst)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    vals = F.device_values(plan, inst)
+    log(f"star join: plan {t_plan:.1f} s")
+    t_fwd, R, _ = time_forward(plan, vals, steps, warmup)
+    t_fb = time_steps(lambda: fwd_bwd_step(plan, vals), steps, warmup)
+    out = {"workload": "star join: fact 10^7 rows x 8 cols with 4 uniform foreign keys into four "
+                       "10^5-row dimensions x 8 cols; column scales 10^U[-3,3]; n = 40",
+           "tuples": inst.M, "join_rows": plan.join_rows, "plan_s": t_plan,
+           "fwd_ms": t_fwd * 1e3, "fwd_tuples_per_s": inst.M / t_fwd,
+           "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_tuples_per_s": inst.M / t_fb}
+    if with_comparator:
+        log("star join: materialising 10^7 x 40 for the comparator")
+        t0 = time.perf_counter()
+        Ah = oracle.join(inst)
+        A = torch.as_tensor(Ah).cuda()       # Fortran-ordered host array -> (rows, n) view
+        torch.cuda.synchronize()
+        t_mat = time.perf_counter() - t0
+        t_qr, Rq = materialized_qr_ms(A)
+        G = A.t() @ A
+        gn = torch.linalg.norm(G)
+
+        def gram_res(Rx):
+            return float(torch.linalg.norm(Rx.t() @ Rx - G) / gn)
+
+        out["comparator"] = {
+            "materialized_qr_ms": t_qr, "materialize_host_ms": t_mat * 1e3,
+            "speedup_fwd": t_qr / (t_fwd * 1e3),
+            "figaro_gram_residual": gram_res(R.contiguous()),
+            "materialized_qr_gram_residual": gram_res(Rq),
+            "rel_diff_R": float(torch.linalg.norm(R - Rq) / torch.linalg.norm(Rq)),
+            "reference": "||R^T R - A^T A|| / ||A^T A|| with A^T A of the materialised join in FP64"}
+        del G
+        del A, Ah
+        torch.cuda.empty_cache()
+    plan.close()
+    return out
+
+
+def traffic_bytes(kernel: str):
+    """Calibrated HBM bytes per launch of `kernel` from the stored rocprofv3
+    counter summary, or None when missing or stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_class") != kernel or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return float(t["hbm_bytes_per_launch"])
 
 
 def main():
@@ -109,8 +224,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
-    ap.add_argument("--cpu-div", type=int, default=400)
+    ap.add_argument("--no-star", action="store_true")
+    ap.add_argument("--cpu-div", type=int, default=100)
     ap.add_argument("--comparator-div", type=int, default=200)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="after timing, copy 256 MiB once (byte calibration for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -123,7 +241,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    log("generating config-2 inputs")
+    log("generating the two-relation inputs")
     inst = synth.config2()
     t0 = time.perf_counter()
     plan = F.plan_from_instance(inst)
@@ -137,15 +255,23 @@ def main():
     M = inst.M
     value = M / t_step
     log(f"forward {t_step * 1e3:.3f} ms/step, {value:.4e} tuples/s")
+    t_fb = time_steps(lambda: fwd_bwd_step(plan, vals), args.steps, args.warmup)
+    log(f"forward+backward {t_fb * 1e3:.3f} ms/step")
+    if args.calibration_copy:
+        a = torch.empty(256 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     # dominant kernel: the class with the largest total time
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    name, (ms, launches, nbytes, flops) = dom
+    name, (ms, launches, nbytes, flops) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_s = ms / 1e3 / max(launches, 1)
     bytes_per_launch = nbytes / max(launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9
+    tb = traffic_bytes(name)
     roofline = {"kernel": name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "fp64_tflops": flops / max(launches, 1) / avg_s / 1e12}
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
@@ -156,12 +282,19 @@ def main():
     out = {"metric": "tuples/s to R (FP64), forward", "value": value, "unit": "tuples/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded, config-2 shape)",
-           "config": {"workload": "two-relation join, 2x2,000,000 tuples, 1000 Zipf(1.1) keys, "
-                                  "16+16 FP64 columns (n=32)",
-                      "tuples": M, "join_rows": plan.join_rows, "n": plan.n,
-                      "plan_s": t_plan},
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
+           "config": {"workload": "two-relation join, 2 x 2,000,000 tuples, 1000 Zipf(1.1) keys, "
+                                  "16 + 16 FP64 columns (n = 32)",
+                      "tuples": M, "join_rows": plan.join_rows, "n": plan.n, "plan_s": t_plan},
+           "fwd_bwd": {"ms_per_step": t_fb * 1e3, "tuples_per_s": M / t_fb,
+                       "loss": "R_nn^2/2 + sum log R_ii"},
+           "join_rows_per_s": plan.join_rows / t_step,
            "roofline": roofline, "kernels": kernels}
+    plan.close()
+    del vals
+    torch.cuda.empty_cache()
+    if not args.no_star:
+        out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator)
     if not args.no_comparator:
         log("comparator: materialised QR on a subsample")
         out["comparator"] = comparator(F, args.comparator_div)
@@ -169,7 +302,7 @@ def main():
         log("cpu baseline: oracle on a subsample")
         v, secs, Ms, rows = cpu_baseline(args.cpu_div)
         out["cpu_baseline"] = {"value": v, "unit": "tuples/s", "cores": 1, "kind": "oracle",
-                               "sample": f"config-2 shape / {args.cpu_div}: {Ms} tuples, {rows} join rows "
+                               "sample": f"two-relation join / {args.cpu_div}: {Ms} tuples, {rows} join rows "
                                          f"materialised, textbook Householder ({secs:.1f} s)"}
     print(json.dumps(out), flush=True)
 
