@@ -11,6 +11,7 @@
 
 #include "internal.hpp"
 #include "device_common.hpp"
+#include "tails.hpp"
 
 namespace figaro {
 namespace {
@@ -60,9 +61,18 @@ __global__ __launch_bounds__(64) void k_qr_adjoint(const double *R, const double
 }
 
 // Backward of one head/tail level; see HelmertBwdArgs.  Chunks are
-// independent here (no accumulation), one or more per wave.
+// independent here (no accumulation), one or more per wave.  The block of K
+// that the level's rows touch is staged in LDS; the tails are recomputed
+// (tile_tails) and replaced by dT = T K_blk; the suffix sums over each piece
+// run as a forward segmented scan over the lanes in reverse order.
 template <int NB, int RPL, int MODE>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
+    __shared__ double sK[NB * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[c]], zero outside ncols
+    for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
+        const int e = i / NB, c = i % NB;
+        sK[i] = (e < a.ncols && c < a.ncols) ? a.K[(int64_t)a.colmap[c] * a.n_total + a.colmap[e]] : 0.0;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
     if (wave >= a.waves) return;
@@ -70,132 +80,70 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
     const int64_t c_end = a.nchunks * (wave + 1) / a.waves;
     for (int64_t ch = c_begin; ch < c_end; ++ch) {
         const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
-        const int64_t base = cs + (int64_t)lane * RPL;
         double x[RPL][NB];
-        int32_t pid[RPL];
-        bool valid[RPL], first[RPL];
+        TileItems<RPL> ti;
+        tile_tails<NB, RPL, MODE, false>(a, cs, ce, lane, x, ti);
+        // dT = T K_blk, two rows at a time (each K row read serves both).  The
+        // LDS offset is opaque to the compiler, so the reads of K are not
+        // hoisted out of the chunk loop (all of K would not fit in registers).
+        int koff = 0;
+        asm volatile("" : "+v"(koff));
+        constexpr int KB = (RPL % 2 == 0) ? 2 : 1;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            valid[k] = base + k < ce;
-            pid[k] = valid[k] ? a.pid[base + k] : -1;
-        }
+        for (int k0 = 0; k0 < RPL; k0 += KB) {
+            double t[KB][NB];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const bool live = c < a.ncols;
-            const double *col = a.in + (int64_t)(live ? c : 0) * a.ld_in;
+            for (int q = 0; q < KB; ++q)
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) x[k][c] = (live && valid[k]) ? col[base + k] : 0.0;
-        }
-        const int32_t prev_last = __shfl_up(pid[RPL - 1], 1, 64);
+                for (int c = 0; c < NB; ++c) t[q][c] = 0.0;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            const int32_t prev = (k == 0) ? prev_last : pid[k - 1];
-            first[k] = !valid[k] || (k == 0 && lane == 0) || pid[k] != prev;
-        }
-        bool lane_flag = false;
+            for (int e = 0; e < NB; ++e) {
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) lane_flag = lane_flag || first[k];
-        double acc[NB];
+                for (int c = 0; c < NB; ++c) {
+                    const double kv = sK[koff + e * NB + c];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            double sum = 0.0;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) sum = (first[k] ? 0.0 : sum) + x[k][c];
-            acc[c] = sum;
-        }
-        const uint64_t mask = __ballot(lane_flag);
-        segmented_carry<NB>(acc, mask, lane);
-        const int nf0 = __shfl_down((int)first[0], 1, 64);
-        const bool next_first0 = (lane == 63) || (nf0 != 0);
-        // recompute the tails (as in the forward pass)
-        double al[RPL], be[RPL];
-        bool last[RPL];
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            const int64_t t = base + k;
-            al[k] = 0.0;
-            be[k] = 0.0;
-            if (valid[k] && !first[k]) {
-                if constexpr (MODE == 0) {
-                    const double j = (double)(t - a.piece_start[pid[k]]);
-                    const double q = 1.0 / sqrt(j * (j + 1.0));
-                    const double phi = a.phi_piece[pid[k]];
-                    al[k] = phi * j * q;
-                    be[k] = phi * q;
-                } else {
-                    al[k] = a.alpha[t];
-                    be[k] = a.beta[t];
+                    for (int q = 0; q < KB; ++q) t[q][c] = fma(x[k0 + q][e], kv, t[q][c]);
                 }
             }
-            last[k] = valid[k] && ((k + 1 < RPL) ? first[k + 1] : next_first0);
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const double xv = x[k][c];
-                const double run = first[k] ? 0.0 : acc[c];
-                x[k][c] = first[k] ? 0.0 : (al[k] * xv - be[k] * run);
-                acc[c] = run + xv;
-            }
+            for (int q = 0; q < KB; ++q)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) x[k0 + q][c] = t[q][c];
         }
-        // dT = T K_blk (the tail rows' gradient on the block's columns)
-        double g[RPL][NB];
+        // w = beta dT.  Lane aggregate for the lanes below: the items up to
+        // and including the lane's first piece end.
+        double agg[NB];
+        bool lane_last = false;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k)
-#pragma unroll
-            for (int c = 0; c < NB; ++c) g[k][c] = 0.0;
-#pragma unroll
-        for (int e = 0; e < NB; ++e) {
-            if (e >= a.ncols) break;
-            const double *Ke = a.K + (int64_t)a.colmap[e];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                if (c >= a.ncols) break;
-                const double kv = Ke[(int64_t)a.colmap[c] * a.n_total];
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) g[k][c] = fma(x[k][e], kv, g[k][c]);
-            }
-        }
-        // w = beta dT; reverse segmented scan: E_t = sum_{u > t in its piece} w_u
-        bool stop = false, lane_last = false;
-        double A[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) A[c] = 0.0;
+        for (int c = 0; c < NB; ++c) agg[c] = 0.0;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
-            if (!stop) {
+            const double wk = lane_last ? 0.0 : ti.be[k];
 #pragma unroll
-                for (int c = 0; c < NB; ++c) A[c] = fma(be[k], g[k][c], A[c]);
-            }
-            stop = stop || last[k];
-            lane_last = lane_last || last[k];
+            for (int c = 0; c < NB; ++c) agg[c] = fma(wk, x[k][c], agg[c]);
+            lane_last = lane_last || ti.last[k];
         }
-        bool f = lane_last;
+        // suffix scan over the lanes: reverse the lanes, forward segmented
+        // scan (a segment starts at every lane holding a piece end), reverse
+        const int rev = 63 - lane;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const bool pf = __shfl_down((int)f, off, 64) != 0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const double pa = __shfl_down(A[c], off, 64);
-                if (lane + off < 64 && !f) A[c] += pa;
-            }
-            if (lane + off < 64) f = f || pf;
-        }
+        for (int c = 0; c < NB; ++c) agg[c] = __shfl(agg[c], rev, 64);
+        segmented_carry<NB>(agg, __builtin_bitreverse64(__ballot(lane_last)), lane);
         double run[NB];
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const double v = __shfl_down(A[c], 1, 64);
-            run[c] = (lane == 63) ? 0.0 : v;
-        }
+        for (int c = 0; c < NB; ++c) run[c] = __shfl(agg[c], rev, 64);
+        const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
         for (int k = RPL - 1; k >= 0; --k) {
             const int64_t t = base + k;
+            const double lm = ti.last[k] ? 0.0 : 1.0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                const double E = last[k] ? 0.0 : run[c];
-                const double w = be[k] * g[k][c];
-                if (valid[k] && c < a.ncols)
+                const double E = run[c] * lm;
+                if (ti.valid[k] && c < a.ncols)
                     a.gout[(int64_t)c * a.ld_gout + t] =
-                        fma(al[k], g[k][c], -E) + a.gpieces[(int64_t)c * a.ld_gp + pid[k]];
-                run[c] = w + E;
+                        fma(ti.al[k], x[k][c], -E) + a.gpieces[(int64_t)c * a.ld_gp + ti.pid[k]];
+                run[c] = fma(ti.be[k], x[k][c], E);
             }
         }
     }
@@ -226,21 +174,19 @@ __global__ void k_join_bwd(JoinBwdArgs a) {
     }
 }
 
+// Root rows h_g = s_g / sqrt(c_g): dh_g = h_g K, so ds_g[c] = (s_g . K[:, c]) / c_g.
+// One thread per (root group, column c); column c of K is staged in LDS.
 __global__ void k_root_bwd(RootBwdArgs a) {
+    __shared__ double kc[kMaxCols];
+    const int c = blockIdx.y;
+    for (int e = threadIdx.x; e < a.n; e += blockDim.x) kc[e] = a.K[(int64_t)c * a.n + e];
+    __syncthreads();
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.groups) return;
     const double f = a.inv_sqrt_c ? a.inv_sqrt_c[g] : 1.0;
-    double row[kMaxCols];
-#pragma unroll
-    for (int e = 0; e < kMaxCols; ++e) row[e] = (e < a.n) ? a.s[(int64_t)e * a.ld_s + g] * f : 0.0;
-    for (int c = 0; c < a.n; ++c) {
-        const double *Kc = a.K + (int64_t)c * a.n;
-        double d = 0.0;
-#pragma unroll
-        for (int e = 0; e < kMaxCols; ++e)
-            if (e < a.n) d = fma(row[e], Kc[e], d);
-        a.ds[(int64_t)c * a.ld_ds + g] = d * f;
-    }
+    double d = 0.0;
+    for (int e = 0; e < a.n; ++e) d = fma(a.s[(int64_t)e * a.ld_s + g], kc[e], d);
+    a.ds[(int64_t)c * a.ld_ds + g] = d * f * f;
 }
 
 __global__ void k_copy_cols(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
@@ -294,9 +240,9 @@ hipError_t launch_join_bwd(const JoinBwdArgs &a, hipStream_t s) {
 }
 
 hipError_t launch_root_bwd(const RootBwdArgs &a, hipStream_t s) {
-    if (a.groups <= 0) return hipSuccess;
-    const int bs = 128;
-    hipLaunchKernelGGL(k_root_bwd, dim3((unsigned)((a.groups + bs - 1) / bs)), dim3(bs), 0, s, a);
+    if (a.groups <= 0 || a.n <= 0) return hipSuccess;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_root_bwd, dim3((unsigned)((a.groups + bs - 1) / bs), (unsigned)a.n), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

@@ -73,18 +73,19 @@ __device__ __forceinline__ void segmented_carry(double (&acc)[NB], uint64_t mask
     const int row = lane >> 4;
     const bool b15 = (row == 1 || row == 3) && !flag_in(mask, row0, lane);
     const bool b31 = (row >= 2) && !flag_in(mask, 32, lane);
+    // 0/1 factors instead of selects (one FMA per step)
+    const double m1 = a1 ? 1.0 : 0.0, m2 = a2 ? 1.0 : 0.0, m4 = a4 ? 1.0 : 0.0, m8 = a8 ? 1.0 : 0.0;
+    const double m15 = b15 ? 1.0 : 0.0, m31 = b31 ? 1.0 : 0.0, m0 = (lane == 0) ? 0.0 : 1.0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         double v = acc[c];
-        double t;
-        t = dpp<0x111>(v, 0.0); v += a1 ? t : 0.0;   // row_shr:1
-        t = dpp<0x112>(v, 0.0); v += a2 ? t : 0.0;   // row_shr:2
-        t = dpp<0x114>(v, 0.0); v += a4 ? t : 0.0;   // row_shr:4
-        t = dpp<0x118>(v, 0.0); v += a8 ? t : 0.0;   // row_shr:8
-        t = dpp<0x142, 0xA, 0xF, false>(v, 0.0); v += b15 ? t : 0.0;
-        t = dpp<0x143, 0xC, 0xF, false>(v, 0.0); v += b31 ? t : 0.0;
-        const double prev = __shfl_up(v, 1, 64);
-        acc[c] = (lane == 0) ? 0.0 : prev;
+        v = fma(dpp<0x111>(v, 0.0), m1, v);   // row_shr:1
+        v = fma(dpp<0x112>(v, 0.0), m2, v);   // row_shr:2
+        v = fma(dpp<0x114>(v, 0.0), m4, v);   // row_shr:4
+        v = fma(dpp<0x118>(v, 0.0), m8, v);   // row_shr:8
+        v = fma(dpp<0x142, 0xA, 0xF, false>(v, 0.0), m15, v);
+        v = fma(dpp<0x143, 0xC, 0xF, false>(v, 0.0), m31, v);
+        acc[c] = __shfl_up(v, 1, 64) * m0;
     }
 }
 

@@ -22,6 +22,7 @@
 
 #include "internal.hpp"
 #include "device_common.hpp"
+#include "tails.hpp"
 
 namespace figaro {
 namespace {
@@ -308,86 +309,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
         } else {
             const int64_t ch = c_begin + it;
             const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
-            const int64_t base = cs + (int64_t)lane * RPL;
-            int32_t pid[RPL];
-            bool valid[RPL], first[RPL];
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                valid[k] = base + k < ce;
-                pid[k] = valid[k] ? a.pid[base + k] : -1;
-            }
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const bool live = c < a.ncols;
-                const double *col = a.in + (int64_t)(live ? c : 0) * a.ld_in;
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) x[k][c] = (live && valid[k]) ? col[base + k] : 0.0;
-            }
-            // piece starts: the chunk's first item, and every change of piece id
-            const int32_t prev_last = __shfl_up(pid[RPL - 1], 1, 64);
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const int32_t prev = (k == 0) ? prev_last : pid[k - 1];
-                first[k] = !valid[k] || (k == 0 && lane == 0) || pid[k] != prev;
-            }
-            bool lane_flag = false;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) lane_flag = lane_flag || first[k];
-            // per-lane aggregate since the lane's last piece start
-            double acc[NB];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                double sum = 0.0;
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) sum = (first[k] ? 0.0 : sum) + x[k][c];
-                acc[c] = sum;
-            }
-            const uint64_t mask = __ballot(lane_flag);
-            segmented_carry<NB>(acc, mask, lane);
-            // (shuffle unconditionally: a shuffle under a divergent mask would
-            // read an inactive lane)
-            const int nf0 = __shfl_down((int)first[0], 1, 64);
-            const bool next_first0 = (lane == 63) || (nf0 != 0);
-            // tails, piece sums
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const int64_t t = base + k;
-                double al = 0.0, be = 0.0;
-                if constexpr (MODE == 0) {
-                    if (valid[k] && !first[k]) {
-                        const double j = (double)(t - a.piece_start[pid[k]]);
-                        const double q = 1.0 / sqrt(j * (j + 1.0));
-                        const double phi = a.phi_piece[pid[k]];
-                        al = phi * j * q;
-                        be = phi * q;
-                    }
-                } else {
-                    // branch-free: every lane loads (a clamped index for
-                    // items past the end), the piece start selects zero
-                    const int64_t tc = valid[k] ? t : cs;
-                    const double a0 = a.alpha[tc], b0 = a.beta[tc];
-                    const bool use = valid[k] && !first[k];
-                    al = use ? a0 : 0.0;
-                    be = use ? b0 : 0.0;
-                }
-                const bool last = valid[k] && ((k + 1 < RPL) ? first[k + 1] : next_first0);
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const double xv = x[k][c];
-                    const double run = first[k] ? 0.0 : acc[c];
-                    x[k][c] = first[k] ? 0.0 : (al * xv - be * run);
-                    acc[c] = run + xv;
-                }
-                if (last && a.pieces_out) {
-#pragma unroll
-                    for (int c = 0; c < NB; ++c)
-                        if (c < a.ncols) a.pieces_out[(int64_t)c * a.ld_pieces + pid[k]] = acc[c];
-                }
-            }
+            TileItems<RPL> ti;
+            tile_tails<NB, RPL, MODE, true>(a, cs, ce, lane, x, ti);
             if constexpr (!FUSE) {
+                const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
                 for (int k = 0; k < RPL; ++k) {
-                    if (!valid[k] || !a.r0) continue;
+                    if (!ti.valid[k] || !a.r0) continue;
                     const int64_t row = a.r0_row0 + base + k;
 #pragma unroll
                     for (int c = 0; c < NB; ++c)
