@@ -68,6 +68,7 @@ __global__ __launch_bounds__(64) void k_qr_adjoint(const double *R, const double
 template <int NB, int RPL, int MODE>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
     __shared__ double sK[NB * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[c]], zero outside ncols
+    __shared__ double stage[kWavesPerBlock * 64 * RPL];   // per-wave store staging
     for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
         const int e = i / NB, c = i % NB;
         sK[i] = (e < a.ncols && c < a.ncols) ? a.K[(int64_t)a.colmap[c] * a.n_total + a.colmap[e]] : 0.0;
@@ -132,46 +133,89 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
         double run[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) run[c] = __shfl(agg[c], rev, 64);
-        const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
         for (int k = RPL - 1; k >= 0; --k) {
-            const int64_t t = base + k;
             const double lm = ti.last[k] ? 0.0 : 1.0;
+            const int32_t pk = ti.valid[k] ? ti.pid[k] : 0;
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
                 const double E = run[c] * lm;
-                if (ti.valid[k] && c < a.ncols)
-                    a.gout[(int64_t)c * a.ld_gout + t] =
-                        fma(ti.al[k], x[k][c], -E) + a.gpieces[(int64_t)c * a.ld_gp + ti.pid[k]];
+                const double gp = (c < a.ncols) ? a.gpieces[(int64_t)c * a.ld_gp + pk] : 0.0;
+                const double out = fma(ti.al[k], x[k][c], -E) + gp;
                 run[c] = fma(ti.be[k], x[k][c], E);
+                x[k][c] = out;
+            }
+        }
+        const int64_t nitems = ce - cs;
+        if (a.gout_rowmajor) {
+            // rows of the lane's items are contiguous in a row-major output
+            const int64_t base = cs + (int64_t)lane * RPL;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (ti.valid[k]) {
+                    double *row = a.gout + (base + k) * a.ld_gout;
+#pragma unroll
+                    for (int c = 0; c < NB; ++c)
+                        if (c < a.ncols) row[c] = x[k][c];
+                }
+            continue;
+        }
+        // coalesced stores: per column, the lane-contiguous items go through
+        // the wave's LDS slice and come back lane-strided (same wave: LDS
+        // accesses complete in order, no barrier needed)
+        double *st = stage + (threadIdx.x >> 6) * (64 * RPL);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            // (a guard, not a break: a break would stop the unrolling and
+            // send x to scratch memory)
+            if (c < a.ncols) {
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) st[lane * RPL + k] = x[k][c];
+                double v[RPL];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) v[k] = st[k * 64 + lane];
+                double *dst = a.gout + (int64_t)c * a.ld_gout + cs;
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                    if (k * 64 + lane < nitems) dst[k * 64 + lane] = v[k];
             }
         }
     }
 }
 
+// Backward of process_and_join_children.  Part 0: one thread per (own
+// column c, key group g): dOwn[c][g] = ds[g][own_pos + c] * own_mult[g].
+// Part 1 + j: one thread per (group q of child j, column c): the sum over
+// the parent key groups g with cidx_j[g] = q (the plan's inverse index, a
+// fixed order, so the result is deterministic) of ds[g][colpos_j[c]] *
+// mult_j[g].  ds is row-major, so the threads of one q read one row.
 __global__ void k_join_bwd(JoinBwdArgs a) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int part = blockIdx.y;
     if (part == 0) {
-        if (i >= a.groups) return;
-        const double om = a.own_mult[i];
-        for (int c = 0; c < a.own_cols; ++c)
-            a.dOwn[(int64_t)c * a.ld_own + i] = a.ds[(int64_t)(a.own_pos + c) * a.ld_ds + i] * om;
+        if (a.own_cols <= 0 || a.groups <= 0) return;
+        const int c = (int)(idx / a.groups);
+        const int64_t g = idx - (int64_t)c * a.groups;
+        if (c >= a.own_cols) return;
+        a.dOwn[(int64_t)c * a.ld_own + g] = a.ds[g * a.ld_ds + a.own_pos + c] * a.own_mult[g];
         return;
     }
     const int j = part - 1;
-    if (i >= a.child_groups[j]) return;
-    const int64_t lo = a.inv_off[j][i], hi = a.inv_off[j][i + 1];
-    const int32_t *pos = a.colpos[j];
-    for (int c = 0; c < a.child_cols[j]; ++c) {
-        const double *src = a.ds + (int64_t)pos[c] * a.ld_ds;
-        double sum = 0.0;
-        for (int64_t q = lo; q < hi; ++q) {
-            const int32_t g = a.inv_idx[j][q];
-            sum = fma(src[g], a.mult[j][g], sum);
-        }
-        a.dsigma[j][(int64_t)c * a.ld_dsigma[j] + i] = sum;
+    const int cc = a.child_cols[j];
+    const int64_t q = idx / cc;
+    const int c = (int)(idx - q * cc);
+    if (q >= a.child_groups[j]) return;
+    const int64_t lo = a.inv_off[j][q], hi = a.inv_off[j][q + 1];
+    const int col = a.colpos[j][c];
+    const int32_t *inv = a.inv_idx[j];
+    const double *mult = a.mult[j];
+    double sum = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+        const int64_t g = inv[i];
+        sum = fma(a.ds[g * a.ld_ds + col], mult[g], sum);
     }
+    if (a.dsigma_rowmajor[j]) a.dsigma[j][q * a.ld_dsigma[j] + c] = sum;
+    else a.dsigma[j][(int64_t)c * a.ld_dsigma[j] + q] = sum;
 }
 
 // Root rows h_g = s_g / sqrt(c_g): dh_g = h_g K, so ds_g[c] = (s_g . K[:, c]) / c_g.
@@ -186,7 +230,8 @@ __global__ void k_root_bwd(RootBwdArgs a) {
     const double f = a.inv_sqrt_c ? a.inv_sqrt_c[g] : 1.0;
     double d = 0.0;
     for (int e = 0; e < a.n; ++e) d = fma(a.s[(int64_t)e * a.ld_s + g], kc[e], d);
-    a.ds[(int64_t)c * a.ld_ds + g] = d * f * f;
+    if (a.ds_rowmajor) a.ds[g * a.ld_ds + c] = d * f * f;
+    else a.ds[(int64_t)c * a.ld_ds + g] = d * f * f;
 }
 
 __global__ void k_copy_cols(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
@@ -231,11 +276,13 @@ hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s)
 }
 
 hipError_t launch_join_bwd(const JoinBwdArgs &a, hipStream_t s) {
-    int64_t mx = a.groups;
-    for (int j = 0; j < a.nchildren; ++j) mx = std::max(mx, a.child_groups[j]);
+    int64_t mx = a.groups * std::max(a.own_cols, 0);
+    for (int j = 0; j < a.nchildren; ++j) mx = std::max(mx, a.child_groups[j] * a.child_cols[j]);
     if (mx <= 0) return hipSuccess;
     const int bs = 256;
-    hipLaunchKernelGGL(k_join_bwd, dim3((unsigned)((mx + bs - 1) / bs), 1 + a.nchildren), dim3(bs), 0, s, a);
+    const int64_t blocks = (mx + bs - 1) / bs;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_join_bwd, dim3((unsigned)blocks, 1 + a.nchildren), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

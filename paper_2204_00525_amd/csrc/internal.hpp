@@ -98,8 +98,9 @@ struct HelmertBwdArgs {
     int8_t colmap[64];
     const double *gpieces;       // gradient of the piece sums, [ncols][ld_gp]
     int64_t ld_gp;
-    double *gout;                // gradient of the items, [ncols][ld_gout]
+    double *gout;                // gradient of the items, [ncols][ld_gout] (or [items][ld_gout])
     int64_t ld_gout;
+    int32_t gout_rowmajor;       // 1: item t, column c at gout[t * ld_gout + c]
     int32_t waves;
 };
 
@@ -148,7 +149,7 @@ struct RootArgs {
 // that join it (plan-time inverse index, deterministic order).
 struct JoinBwdArgs {
     int64_t groups;
-    const double *ds;            // [nsub][ld_ds]
+    const double *ds;            // row-major [groups][ld_ds] (ld_ds >= nsub)
     int64_t ld_ds;
     double *dOwn;                // [own_cols][ld_own]
     int64_t ld_own;
@@ -158,6 +159,7 @@ struct JoinBwdArgs {
     int32_t nchildren;
     double *dsigma[kMaxChildren];
     int64_t ld_dsigma[kMaxChildren];
+    int32_t dsigma_rowmajor[kMaxChildren];
     int64_t child_groups[kMaxChildren];
     int32_t child_cols[kMaxChildren];
     const int32_t *colpos[kMaxChildren];
@@ -177,6 +179,7 @@ struct RootBwdArgs {
     const double *K;
     double *ds;
     int64_t ld_ds;
+    int32_t ds_rowmajor;         // 1: group g, column c at ds[g * ld_ds + c]
 };
 
 // ---------------------------------------------------------------------------

@@ -223,9 +223,13 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
     return FIGARO_OK;
 }
 
+// Where a gradient goes: column-major [cols][ld] unless rowmajor ([rows][ld]).
+// The gradients of the joined heads (d_gs) are row-major, which keeps the
+// gathers of the join's adjoint within one row per key group.
 struct Target {
     double *p;
     int64_t ld;
+    bool rowmajor = false;
 };
 
 // Where the gradient of the key-group sums of relation v goes: the top level
@@ -242,7 +246,7 @@ Target sigma_grad_target(figaro_plan_s *p, int v, double *const *dvalues, const 
     RelPlan &R = p->rel[v];
     if (R.children.empty()) return own_grad_target(p, v, dvalues, ld_dv);
     if (R.a4.active) return {R.a4.levels.back().d_gpieces, R.a4.levels.back().npieces};
-    return {R.d_gs, R.G};
+    return {R.d_gs, R.nsub, true};
 }
 
 // Backward of the levels of one task, top level first; level 0 writes the
@@ -268,6 +272,7 @@ figaro_status run_task_bwd(figaro_plan_s *p, Task &T, const double *in, int64_t 
         a.ld_gp = L.npieces;
         a.gout = (l == 0) ? out.p : T.levels[l - 1].d_gpieces;
         a.ld_gout = (l == 0) ? out.ld : T.levels[l - 1].npieces;
+        a.gout_rowmajor = (l == 0 && out.rowmajor) ? 1 : 0;
         a.waves = (int32_t)std::min<int64_t>(L.nchunks, 8192);
         ProfScope ps(p, s, 6, 8.0 * (double)L.items * T.ncols * 2.0, 2.0 * (double)L.items * T.ncols * T.ncols);
         FIGARO_TRY(launch_helmert_bwd(a, L.unit, s));
@@ -292,7 +297,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
         // items of v after the join (s), and where their gradient lives
         const double *items = leaf ? B.own[v] : Rl.d_s;
         const int64_t ld_items = leaf ? B.ld_own[v] : Rl.G;
-        const Target gs = leaf ? own_grad_target(p, v, dvalues, ld_dv) : Target{Rl.d_gs, Rl.G};
+        const Target gs = leaf ? own_grad_target(p, v, dvalues, ld_dv) : Target{Rl.d_gs, Rl.nsub, true};
         if (Rl.parent < 0) {
             RootBwdArgs ra{};
             ra.groups = Rl.G;
@@ -303,6 +308,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
             ra.K = p->d_K;
             ra.ds = gs.p;
             ra.ld_ds = gs.ld;
+            ra.ds_rowmajor = gs.rowmajor ? 1 : 0;
             ProfScope ps(p, s, 6, 16.0 * (double)Rl.G * p->n, 0.0);
             FIGARO_TRY(launch_root_bwd(ra, s));
         } else if (!leaf && Rl.a4.active) {
@@ -313,7 +319,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
             JoinBwdArgs j{};
             j.groups = Rl.G;
             j.ds = Rl.d_gs;
-            j.ld_ds = Rl.G;
+            j.ld_ds = Rl.nsub;
             const Target own = own_grad_target(p, v, dvalues, ld_dv);
             j.dOwn = own.p;
             j.ld_own = own.ld;
@@ -326,6 +332,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
                 const Target t = sigma_grad_target(p, ch, dvalues, ld_dv);
                 j.dsigma[c] = t.p;
                 j.ld_dsigma[c] = t.ld;
+                j.dsigma_rowmajor[c] = t.rowmajor ? 1 : 0;
                 j.child_groups[c] = p->rel[ch].P;
                 j.child_cols[c] = p->rel[ch].nsub;
                 j.colpos[c] = Rl.d_colpos[c];
