@@ -21,7 +21,9 @@ Also reported on the same line:
     or null when the kernel source changed since they were taken;
   * cpu_baseline: the CPU oracle timed on a bounded sample;
   * comparator: torch.linalg.qr of the materialised two-relation join on a
-    subsample small enough to materialise, next to this library on it.
+    subsample small enough to materialise, next to this library on it;
+  * batched: many independent instances of the batched workload in one call
+    (eager and as a replayed HIP graph), forward and forward + backward.
 """
 from __future__ import annotations
 
@@ -204,6 +206,65 @@ def star(F, steps, warmup, with_comparator):
     return out
 
 
+def batched(F, count, steps, warmup):
+    """The batched workload: the first `count` instances (seeds 5000+i) with
+    at most 64 columns, one plan each, run as one batch on 8 streams, eager
+    and replayed from a captured HIP graph, next to the same plans run one
+    after another on one stream."""
+    import torch
+    import synth
+    ids, insts = [], []
+    for i in range(count):
+        inst = synth.config5_instance(i)
+        if sum(r.values.shape[0] for r in inst.rels) <= 64:
+            ids.append(i)
+            insts.append(inst)
+    log(f"batched: {len(insts)} instances, planning")
+    t0 = time.perf_counter()
+    plans = [F.plan_from_instance(inst) for inst in insts]
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    vals = [F.device_values(p, inst) for p, inst in zip(plans, insts)]
+    M = sum(inst.M for inst in insts)
+    b = F.Batch(plans, streams=8)
+    t_eager = time_steps(lambda: b.r(vals), steps, warmup)
+    s = torch.cuda.Stream()
+    outs = [torch.empty((p.n, p.n), dtype=torch.float64, device="cuda") for p in plans]
+    with torch.cuda.stream(s):
+        b.capture(vals, outs, s)
+    s.synchronize()
+
+    def replay():
+        b.launch(s)
+
+    for _ in range(warmup):
+        replay()
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        replay()
+    s.synchronize()
+    t_graph = (time.perf_counter() - t0) / steps
+    t_seq = time_steps(lambda: [p.r_factor(v) for p, v in zip(plans, vals)], steps, warmup)
+
+    def fb():
+        Rs = b.r(vals)
+        return b.r_backward(vals, Rs, [loss_grad(R) for R in Rs])
+
+    t_fb = time_steps(fb, max(2, steps // 2), 1)
+    out = {"workload": f"batched joins: instances {ids[0]}..{ids[-1]} of the 512 (seeds 5000+i) with n <= 64 "
+                       f"({len(insts)} of the first {count}); 2-4 relations, chains and stars, 1e3-1e6 tuples "
+                       "per relation, uniform or Zipf keys",
+           "instances": len(insts), "tuples": M, "plan_s": t_plan,
+           "fwd_ms_eager": t_eager * 1e3, "fwd_ms_graph": t_graph * 1e3, "fwd_ms_one_stream": t_seq * 1e3,
+           "fwd_tuples_per_s_graph": M / t_graph, "fwd_bwd_ms_eager": t_fb * 1e3,
+           "fwd_bwd_tuples_per_s": M / t_fb}
+    b.close()
+    for p in plans:
+        p.close()
+    return out
+
+
 def traffic_bytes(kernel: str):
     """Calibrated HBM bytes per launch of `kernel` from the stored rocprofv3
     counter summary, or None when missing or stale."""
@@ -225,6 +286,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-star", action="store_true")
+    ap.add_argument("--batched", type=int, default=48,
+                    help="instances of the batched workload to consider (0: skip)")
     ap.add_argument("--cpu-div", type=int, default=100)
     ap.add_argument("--comparator-div", type=int, default=200)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -295,6 +358,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_star:
         out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator)
+    if args.batched > 0:
+        out["batched"] = batched(F, args.batched, max(3, args.steps // 2), 2)
     if not args.no_comparator:
         log("comparator: materialised QR on a subsample")
         out["comparator"] = comparator(F, args.comparator_div)

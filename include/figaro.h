@@ -238,6 +238,67 @@ figaro_status figaro_profile_reset(figaro_plan_t plan);
 /* Message of the last failing call on `plan` (NULL: on the calling thread). */
 const char *figaro_last_error(figaro_plan_t plan);
 
+/*
+ * Batches: many independent join instances (each with its own plan) in one
+ * call, for serving.  Each instance is the computation of figaro_r (or
+ * figaro_r_backward) on its own plan; the paper treats one join at a time,
+ * and a batch is simply the independent instances side by side.
+ *
+ * figaro_batch_create() takes `count` distinct plans (the batch does not own
+ * them; they must outlive it) and creates `streams` HIP streams (<= 0: 8) of
+ * default priority; instances are assigned to streams longest-first by an
+ * estimate of their work.  Errors: FIGARO_EINVAL for a NULL, analyze-only or
+ * repeated plan; FIGARO_EHIP if a stream or event cannot be created.
+ * Messages go to figaro_last_error(NULL).
+ *
+ * figaro_r_batched(): R[i] <- R of instance i, with values[i] / ld[i] as for
+ * figaro_r on plans[i] (plan order, device).  The batch forks from `stream`
+ * with an event, runs every instance on its assigned stream, and joins back
+ * into `stream`: work enqueued later on `stream` sees every R.  No
+ * allocation, no host synchronisation.  On an argument error in instance i
+ * the other instances still run; the first error is returned.
+ *
+ * figaro_r_backward_batched(): the same for figaro_r_backward, per instance.
+ *
+ * figaro_batch_capture(): captures the sequence of figaro_r_batched() with
+ * these pointers into a HIP graph (stream capture on `stream`, which must not
+ * be the null stream; profiling must be disabled on every plan), replacing
+ * any graph captured before.  figaro_batch_launch() replays it on a stream:
+ * the buffers captured are read and written again.  Concurrent use of one
+ * batch (or of its plans) must be serialised by the caller.
+ */
+typedef struct figaro_batch_s *figaro_batch_t;
+figaro_status figaro_batch_create(figaro_batch_t *out, int32_t count, const figaro_plan_t *plans,
+                                  int32_t streams);
+void figaro_batch_destroy(figaro_batch_t batch);
+int32_t figaro_batch_stream_of(figaro_batch_t batch, int32_t instance);   /* -1 if out of range */
+figaro_status figaro_r_batched(figaro_batch_t batch, const double *const *const *values,
+                               const int64_t *const *ld, double *const *R, hipStream_t stream);
+figaro_status figaro_r_backward_batched(figaro_batch_t batch, const double *const *const *values,
+                                        const int64_t *const *ld, const double *const *R,
+                                        const double *const *dR, double *const *const *dvalues,
+                                        const int64_t *const *ld_dvalues, hipStream_t stream);
+figaro_status figaro_batch_capture(figaro_batch_t batch, const double *const *const *values,
+                                   const int64_t *const *ld, double *const *R, hipStream_t stream);
+figaro_status figaro_batch_launch(figaro_batch_t batch, hipStream_t stream);
+
+/*
+ * Autotuner: builds the plan under each option set of `candidates`
+ * (ncandidates <= 0 or NULL: register-tile variants 0 and 2 times wave caps
+ * 512, 1024, 2048; analyze_only is ignored), times `reps` forward passes of
+ * each on the caller's values (values[i]: device, caller order, column-major,
+ * ld[i] >= rows; they are copied into plan order in a temporary buffer), and
+ * returns the fastest plan.  Candidates the instance cannot use are skipped;
+ * FIGARO_EUNSUPPORTED if none works.  Allocates and synchronises `stream`
+ * (a planning call, not a compute call).  figaro_plan_tuning() reports the
+ * option set chosen and its time per pass in milliseconds (FIGARO_EINVAL for
+ * a plan not built here).
+ */
+figaro_status figaro_plan_create_tuned(figaro_plan_t *out, int32_t r, const figaro_relation_desc *relations,
+                                       const double *const *values, const int64_t *ld, int32_t ncandidates,
+                                       const figaro_plan_options *candidates, int32_t reps, hipStream_t stream);
+figaro_status figaro_plan_tuning(figaro_plan_t plan, figaro_plan_options *chosen, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,17 @@ def lib():
         "figaro_debug_stack": (i32, [vp, pp, pi64, vp, vp]),
         "figaro_debug_stack_layout": (i32, [vp, pi64, i32]),
         "figaro_debug_tile_rows": (i64, [i32, i32]),
+        "figaro_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32]),
+        "figaro_batch_destroy": (None, [vp]),
+        "figaro_batch_stream_of": (i32, [vp, i32]),
+        "figaro_r_batched": (i32, [vp, ctypes.POINTER(pp), ctypes.POINTER(pi64), pp, vp]),
+        "figaro_r_backward_batched": (i32, [vp, ctypes.POINTER(pp), ctypes.POINTER(pi64), pp, pp,
+                                            ctypes.POINTER(pp), ctypes.POINTER(pi64), vp]),
+        "figaro_batch_capture": (i32, [vp, ctypes.POINTER(pp), ctypes.POINTER(pi64), pp, vp]),
+        "figaro_batch_launch": (i32, [vp, vp]),
+        "figaro_plan_create_tuned": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(RelationDesc), pp, pi64, i32,
+                                           ctypes.POINTER(PlanOptions), i32, vp]),
+        "figaro_plan_tuning": (i32, [vp, ctypes.POINTER(PlanOptions), ctypes.POINTER(dbl)]),
         "figaro_debug_dense_step": (i32, [i32, i64, vp, i64, i32, i64, i32, vp, i64, vp, vp]),
     }
     optional = {
@@ -121,6 +132,31 @@ def _ptr(t) -> int:
     return t.data_ptr()
 
 
+def _device_descs(relations):
+    """Relation descriptors for device key tensors; returns (descs, keepalive)."""
+    import torch
+    r = len(relations)
+    descs = (RelationDesc * r)()
+    keep = []
+    for i, rel in enumerate(relations):
+        attrs = np.ascontiguousarray(np.asarray(rel.key_attrs, dtype=np.int32))
+        keys = rel.keys
+        if keys.numel() and not keys.is_cuda:
+            raise ValueError("key columns must be device tensors")
+        keys = keys.contiguous()
+        keep += [attrs, keys]
+        descs[i].rows = int(keys.shape[1]) if keys.dim() == 2 else 0
+        descs[i].num_keys = len(rel.key_attrs)
+        descs[i].key_attr = attrs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        descs[i].key_cols = ctypes.c_void_p(keys.data_ptr() if keys.numel() else 0)
+        descs[i].key_dtype = 8 if keys.dtype == torch.int64 else 4
+        descs[i].num_cols = int(rel.ncols)
+        descs[i].parent = int(rel.parent)
+        if hasattr(rel, "rows_override"):
+            descs[i].rows = int(rel.rows_override)
+    return descs, keep
+
+
 class Plan:
     """A plan over one key structure: validated join tree, reduced and sorted
     relations, exact count queries, scale factors and a device workspace.
@@ -130,42 +166,69 @@ class Plan:
     and parent (int, -1 for the root)."""
 
     def __init__(self, relations: Sequence, *, tile_items: int = 0, waves_per_task: int = 0,
-                 stream=None, analyze_only: bool = False, variant: int = 0):
+                 stream=None, analyze_only: bool = False, variant: int = 0, _handle=None):
         L = lib()
         if analyze_only:
             self._init_host(relations, tile_items, waves_per_task)
             return
+        if _handle is not None:
+            self._handle = _handle
+        else:
+            self._handle = ctypes.c_void_p()
+            descs, keep = _device_descs(relations)
+            opts = PlanOptions(tile_items, waves_per_task, 0, variant, 0)
+            st = L.figaro_plan_create(ctypes.byref(self._handle), len(relations), descs, ctypes.byref(opts),
+                                      _stream_handle(stream))
+            del keep
+            if st != FIGARO_OK:
+                msg = L.figaro_last_error(None)
+                raise FigaroError(st, msg.decode() if msg else "")
+        self.r = len(relations)
+        self.n = L.figaro_plan_num_cols(self._handle)
+        self.ncols = [int(rel.ncols) for rel in relations]
+
+    @classmethod
+    def tuned(cls, relations: Sequence, values: Sequence, candidates=None, reps: int = 3, stream=None):
+        """Autotuned plan: builds the plan under several option sets (tile
+        variant, wave cap), times the forward pass of each on `values`
+        (caller order, (n_i, m_i) float64 device tensors) and keeps the
+        fastest.  `candidates`: list of dicts with keys tile_items,
+        waves_per_task, variant (None: the library's default set)."""
         import torch
-        self._handle = ctypes.c_void_p()
+        L = lib()
+        descs, keep = _device_descs(relations)
         r = len(relations)
-        descs = (RelationDesc * r)()
-        self._keep = []
-        for i, rel in enumerate(relations):
-            attrs = np.ascontiguousarray(np.asarray(rel.key_attrs, dtype=np.int32))
-            keys = rel.keys
-            if keys.numel() and not keys.is_cuda:
-                raise ValueError("key columns must be device tensors")
-            keys = keys.contiguous()
-            self._keep += [attrs, keys]
-            descs[i].rows = int(keys.shape[1]) if keys.dim() == 2 else 0
-            descs[i].num_keys = len(rel.key_attrs)
-            descs[i].key_attr = attrs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-            descs[i].key_cols = ctypes.c_void_p(keys.data_ptr() if keys.numel() else 0)
-            descs[i].key_dtype = 8 if keys.dtype == torch.int64 else 4
-            descs[i].num_cols = int(rel.ncols)
-            descs[i].parent = int(rel.parent)
-            if hasattr(rel, "rows_override"):
-                descs[i].rows = int(rel.rows_override)
-        opts = PlanOptions(tile_items, waves_per_task, 0, variant, 0)
-        st = L.figaro_plan_create(ctypes.byref(self._handle), r, descs, ctypes.byref(opts),
-                                  _stream_handle(stream))
+        ptrs = (ctypes.c_void_p * r)()
+        lds = (ctypes.c_int64 * r)()
+        for i, v in enumerate(values):
+            if v.dtype != torch.float64 or not v.is_cuda or v.stride(1) != 1:
+                raise ValueError("values must be float64 device tensors of shape (n_i, m_i), rows contiguous")
+            ptrs[i] = v.data_ptr()
+            lds[i] = max(v.stride(0), v.shape[1], 1)
+        if candidates:
+            cand = (PlanOptions * len(candidates))()
+            for k, c in enumerate(candidates):
+                cand[k] = PlanOptions(int(c.get("tile_items", 0)), int(c.get("waves_per_task", 0)), 0,
+                                      int(c.get("variant", 0)), 0)
+            nc = len(candidates)
+        else:
+            cand, nc = None, 0
+        h = ctypes.c_void_p()
+        st = L.figaro_plan_create_tuned(ctypes.byref(h), r, descs, ptrs, lds, nc, cand, reps,
+                                        _stream_handle(stream))
+        del keep
         if st != FIGARO_OK:
             msg = L.figaro_last_error(None)
             raise FigaroError(st, msg.decode() if msg else "")
-        self._keep = []
-        self.r = r
-        self.n = L.figaro_plan_num_cols(self._handle)
-        self.ncols = [int(rel.ncols) for rel in relations]
+        return cls(relations, _handle=h)
+
+    def tuning(self):
+        """(chosen options as a dict, milliseconds per forward pass) of a
+        plan built by Plan.tuned()."""
+        o = PlanOptions()
+        ms = ctypes.c_double()
+        _check(lib().figaro_plan_tuning(self._handle, ctypes.byref(o), ctypes.byref(ms)), self._handle)
+        return {"tile_items": o.tile_items, "waves_per_task": o.waves_per_task, "variant": o.variant}, ms.value
 
     def _init_host(self, relations, tile_items, waves_per_task):
         """Keys given as host arrays; only the key analysis runs (validation,
@@ -407,8 +470,8 @@ class _RelView:
         self.parent = parent
 
 
-def plan_from_instance(inst, device="cuda", **kw) -> Plan:
-    """Plan for a synth.Instance-like object (keys moved to the device)."""
+def instance_views(inst, device="cuda") -> List:
+    """Relation views (keys on the device) of a synth.Instance-like object."""
     import torch
     rels = []
     for rel in inst.rels:
@@ -416,7 +479,12 @@ def plan_from_instance(inst, device="cuda", **kw) -> Plan:
         if keys.dim() == 1:
             keys = keys[None, :]
         rels.append(_RelView(list(rel.key_attrs), keys, rel.values.shape[0], rel.parent))
-    return Plan(rels, **kw)
+    return rels
+
+
+def plan_from_instance(inst, device="cuda", **kw) -> Plan:
+    """Plan for a synth.Instance-like object (keys moved to the device)."""
+    return Plan(instance_views(inst, device), **kw)
 
 
 def device_values(plan: Plan, inst, device="cuda") -> List:
@@ -452,3 +520,96 @@ def debug_dense_step(A, workgroups: int, tiles_per_wave: int, variant: int = 0, 
                                          tiles_per_wave, variant, ctypes.c_void_p(out.data_ptr()), workgroups * n,
                                          None, _stream_handle(stream)), None)
     return out.t()
+
+
+class Batch:
+    """Many independent instances (one plan each) per call: instances run
+    side by side on the batch's streams, forked from and joined back to the
+    caller's stream.  capture()/launch() record the whole forward batch once
+    as a HIP graph and replay it."""
+
+    def __init__(self, plans: Sequence[Plan], streams: int = 0):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._handle.value for p in self.plans])
+        self._handle = ctypes.c_void_p()
+        st = lib().figaro_batch_create(ctypes.byref(self._handle), len(self.plans), arr, streams)
+        if st != FIGARO_OK:
+            msg = lib().figaro_last_error(None)
+            raise FigaroError(st, msg.decode() if msg else "")
+
+    def stream_of(self, i: int) -> int:
+        return int(lib().figaro_batch_stream_of(self._handle, i))
+
+    def _marshal(self, values_list):
+        keep, vptrs, lptrs = [], [], []
+        for p, vals in zip(self.plans, values_list):
+            ptrs, lds = p._value_args(vals)
+            keep += [ptrs, lds]
+            vptrs.append(ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)))
+            lptrs.append(ctypes.cast(lds, ctypes.POINTER(ctypes.c_int64)))
+        V = (ctypes.POINTER(ctypes.c_void_p) * len(self.plans))(*vptrs)
+        LD = (ctypes.POINTER(ctypes.c_int64) * len(self.plans))(*lptrs)
+        keep += [V, LD]
+        return V, LD, keep
+
+    def _outs(self, values_list, outs):
+        import torch
+        if outs is None:
+            outs = [torch.empty((p.n, p.n), dtype=torch.float64, device=v[0].device)
+                    for p, v in zip(self.plans, values_list)]
+        R = (ctypes.c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        return outs, R
+
+    def r(self, values_list, outs=None, stream=None):
+        """R of every instance (list of n_i x n_i tensors)."""
+        V, LD, keep = self._marshal(values_list)
+        outs, R = self._outs(values_list, outs)
+        _check(lib().figaro_r_batched(self._handle, V, LD, R, _stream_handle(stream)), None)
+        return [o.T for o in outs]
+
+    def r_backward(self, values_list, Rs, dRs, stream=None):
+        """Gradients of every instance (list of per-relation lists, plan order)."""
+        import torch
+        V, LD, keep = self._marshal(values_list)
+        Rc = [R.detach().T.contiguous() for R in Rs]
+        dRc = [d.detach().to(torch.float64).T.contiguous() for d in dRs]
+        Rp = (ctypes.c_void_p * len(Rc))(*[x.data_ptr() for x in Rc])
+        dRp = (ctypes.c_void_p * len(dRc))(*[x.data_ptr() for x in dRc])
+        grads, gp, gl = [], [], []
+        for p, vals in zip(self.plans, values_list):
+            g = [torch.empty((p.ncols[i], max(p.rows(i), 1)), dtype=torch.float64, device=vals[0].device)
+                 for i in range(p.r)]
+            grads.append(g)
+            a = (ctypes.c_void_p * p.r)(*[x.data_ptr() for x in g])
+            l = (ctypes.c_int64 * p.r)(*[max(x.stride(0), p.rows(i)) for i, x in enumerate(g)])
+            keep += [a, l]
+            gp.append(ctypes.cast(a, ctypes.POINTER(ctypes.c_void_p)))
+            gl.append(ctypes.cast(l, ctypes.POINTER(ctypes.c_int64)))
+        GP = (ctypes.POINTER(ctypes.c_void_p) * len(gp))(*gp)
+        GL = (ctypes.POINTER(ctypes.c_int64) * len(gl))(*gl)
+        _check(lib().figaro_r_backward_batched(self._handle, V, LD, Rp, dRp, GP, GL, _stream_handle(stream)),
+               None)
+        return [[x[:, :p.rows(i)] for i, x in enumerate(g)] for p, g in zip(self.plans, grads)]
+
+    def capture(self, values_list, outs, stream):
+        """Capture the forward batch on these buffers into a HIP graph; `outs`
+        are the n_i x n_i output tensors (written on every launch)."""
+        V, LD, keep = self._marshal(values_list)
+        outs, R = self._outs(values_list, outs)
+        _check(lib().figaro_batch_capture(self._handle, V, LD, R, _stream_handle(stream)), None)
+        self._captured = (values_list, outs, keep)
+        return [o.T for o in outs]
+
+    def launch(self, stream=None):
+        _check(lib().figaro_batch_launch(self._handle, _stream_handle(stream)), None)
+
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            lib().figaro_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -201,6 +201,12 @@ hipError_t launch_root_bwd(const RootBwdArgs &a, hipStream_t s);
 hipError_t launch_copy_cols(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
                             int32_t ncols, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+// Whole passes on one plan (run.cpp), used by the batched entry points.
+figaro_status run_forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, double *R,
+                          hipStream_t s);
+figaro_status run_backward(figaro_plan_s *p, const double *const *values, const int64_t *ld, const double *R,
+                           const double *dR, double *const *dvalues, const int64_t *ld_dv, hipStream_t s);
+
 int tile_items_for(int ncols, int variant);   // items per chunk of the register-tile kernel
 int num_variants();                           // number of register-tile kernel variants
 int dense_tile_rows_for(int ncols, int variant);   // rows per tile of the dense kernel
@@ -320,6 +326,9 @@ struct figaro_plan_s {
     int32_t *d_status = nullptr;     // device status word of the backward pass
     int64_t workspace_bytes = 0;
     std::vector<void *> allocations;
+    // autotuner result (figaro_plan_create_tuned), tuned_ms < 0 otherwise
+    double tuned_ms = -1.0;
+    figaro_plan_options tuned_options{};
     std::string last_error;
     // profiling
     std::vector<hipEvent_t> prof_start, prof_stop;

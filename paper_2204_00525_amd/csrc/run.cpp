@@ -353,6 +353,27 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
 
 }  // namespace
 
+namespace figaro {
+
+figaro_status run_forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, double *R,
+                          hipStream_t s) {
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    return forward(p, values, ld, true, R, nullptr, 0, nullptr, s);
+}
+
+figaro_status run_backward(figaro_plan_s *p, const double *const *values, const int64_t *ld, const double *R,
+                           const double *dR, double *const *dvalues, const int64_t *ld_dv, hipStream_t s) {
+    figaro_status st = check_inputs(p, values, ld);
+    if (st != FIGARO_OK) return st;
+    for (int i = 0; i < p->r; ++i)
+        if (!dvalues[i] || ld_dv[i] < p->rel[i].m)
+            return set_error(p, FIGARO_EINVAL, "dvalues[" + std::to_string(i) + "] is NULL or its ld too small");
+    return backward(p, values, ld, R, dR, dvalues, ld_dv, s);
+}
+
+}  // namespace figaro
+
 extern "C" {
 
 figaro_status figaro_r_backward(figaro_plan_t p, const double *const *values, const int64_t *ld, const double *R,

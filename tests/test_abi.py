@@ -72,3 +72,20 @@ def test_plan_rejects_null_arguments():
     assert F.STATUS_NAMES[L.figaro_plan_create(ctypes.byref(h), 0, None, None, None)] == "EINVAL"
     assert L.figaro_plan_num_cols(None) == -1
     assert F.STATUS_NAMES[L.figaro_r(None, None, None, None, None)] == "EINVAL"
+
+
+def test_batch_rejects_bad_plans():
+    """figaro_batch_create validates its plans before touching the GPU."""
+    import ctypes
+    import paper_2204_00525_amd as F
+    import synth
+    L = F.lib()
+    h = ctypes.c_void_p()
+    assert L.figaro_batch_create(ctypes.byref(h), 0, None, 0) == 1
+    inst = synth.two_relation(1, 50, 40, 2, 2, 5)
+    p = F.Plan(inst.rels, analyze_only=True)
+    arr = (ctypes.c_void_p * 1)(p._handle.value)
+    assert L.figaro_batch_create(ctypes.byref(h), 1, arr, 0) == 1      # analyze-only plan
+    assert b"analyze-only" in L.figaro_last_error(None)
+    arr2 = (ctypes.c_void_p * 2)(p._handle.value, None)
+    assert L.figaro_batch_create(ctypes.byref(h), 2, arr2, 0) == 1     # NULL plan

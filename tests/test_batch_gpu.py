@@ -1,0 +1,110 @@
+"""Batched instances, HIP graph replay and the autotuner (needs an MI355X).
+
+Every instance of a batch is checked against the same plan run alone
+(bit for bit: the same kernels on the same workspace) and against the CPU
+oracle at 1e-10 relative Frobenius error."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# small instances of the batched workload (seeds 5000+i), 2-4 relations,
+# 22-57 columns, chains and stars, uniform and Zipf keys
+INSTANCES = [15, 23, 27, 35, 58, 78, 79, 96]
+
+
+def _relf(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2204_00525_amd as F
+    F.lib()
+    return F
+
+
+@pytest.fixture(scope="module")
+def batch_setup(F):
+    insts = [synth.config5_instance(i) for i in INSTANCES]
+    plans = [F.plan_from_instance(inst) for inst in insts]
+    vals = [F.device_values(p, inst) for p, inst in zip(plans, insts)]
+    return insts, plans, vals
+
+
+def test_batched_forward_matches_single_and_oracle(F, oracle_lib, batch_setup):
+    import torch
+    insts, plans, vals = batch_setup
+    b = F.Batch(plans, streams=3)
+    assert sorted({b.stream_of(i) for i in range(len(plans))}) == [0, 1, 2]
+    Rb = [R.cpu().numpy() for R in b.r(vals)]
+    torch.cuda.synchronize()
+    for inst, p, v, R in zip(insts, plans, vals, Rb):
+        print(f"[batch] {inst.name} n={p.n}", flush=True)
+        Rs = p.r_factor(v).cpu().numpy()
+        assert np.array_equal(R, Rs)
+        assert _relf(R, oracle_lib.r_of_join(inst)) <= 1e-10
+    b.close()
+
+
+def test_graph_replays_match_eager(F, batch_setup):
+    import torch
+    insts, plans, vals = batch_setup
+    b = F.Batch(plans, streams=4)
+    eager = [R.cpu().numpy() for R in b.r(vals)]
+    s = torch.cuda.Stream()
+    outs = [torch.full((p.n, p.n), np.nan, dtype=torch.float64, device="cuda") for p in plans]
+    with torch.cuda.stream(s):
+        Rg = b.capture(vals, outs, s)
+    s.synchronize()
+    for rep in range(3):
+        for o in outs:
+            o.fill_(np.nan)                       # eager work between replays
+        torch.cuda.synchronize()
+        b.launch(s)
+        s.synchronize()
+        for R, E in zip(Rg, eager):
+            assert np.array_equal(R.cpu().numpy(), E), f"replay {rep}"
+    b.close()
+
+
+def test_batched_backward_matches_single(F, batch_setup):
+    import torch
+    insts, plans, vals = batch_setup
+    b = F.Batch(plans)
+    Rs = b.r(vals)
+    dRs = [torch.triu(torch.ones_like(R)) for R in Rs]
+    gb = b.r_backward(vals, Rs, dRs)
+    torch.cuda.synchronize()
+    for p, v, R, dR, g in zip(plans, vals, Rs, dRs, gb):
+        gs = p.r_backward(v, R, dR)
+        for x, y in zip(g, gs):
+            assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+    b.close()
+
+
+def test_duplicate_plan_is_rejected(F, batch_setup):
+    insts, plans, vals = batch_setup
+    with pytest.raises(F.FigaroError) as e:
+        F.Batch([plans[0], plans[1], plans[0]])
+    assert e.value.name == "EINVAL"
+
+
+@pytest.mark.parametrize("i", [15, 35, 96])
+def test_autotuned_plan(F, oracle_lib, i):
+    import torch
+    inst = synth.config5_instance(i)
+    rels = F.instance_views(inst)
+    caller_vals = [torch.as_tensor(np.ascontiguousarray(r.values)).cuda() for r in inst.rels]
+    p = F.Plan.tuned(rels, caller_vals, reps=2)
+    opts, ms = p.tuning()
+    assert opts["variant"] in (0, 2) and opts["waves_per_task"] in (512, 1024, 2048) and ms > 0
+    R = p.r_factor(F.device_values(p, inst)).cpu().numpy()
+    assert _relf(R, oracle_lib.r_of_join(inst)) <= 1e-10
