@@ -23,10 +23,15 @@ figaro_status figaro_debug_stack(figaro_plan_t plan, const double *const *values
  * and a kernel variant (as in figaro_plan_options), or -1 if out of range. */
 int64_t figaro_debug_tile_rows(int32_t n, int32_t variant);
 
+/* Rows that one workgroup of the dense TSQR kernel folds with
+ * tiles_per_wave tile steps (the waves of a workgroup fold separate tiles
+ * for n <= 40 and share each tile for wider matrices), or -1. */
+int64_t figaro_debug_dense_rows(int32_t n, int32_t variant, int64_t tiles_per_wave);
+
 /* One launch of the dense TSQR step (section "Post-processing") on a plain
  * matrix: `in` is a device column-major rows x n matrix (ld_in >= rows);
- * workgroup b folds rows [b*W, (b+1)*W), W = 4 * tiles_per_wave *
- * figaro_debug_tile_rows(n, variant), into one n x n R.  With workgroups ==
+ * workgroup b folds rows [b*W, (b+1)*W), W = figaro_debug_dense_rows(n,
+ * variant, tiles_per_wave), into one n x n R.  With workgroups ==
  * 1 and final_r != NULL the sign-normalised R is written to final_r (n x n,
  * column-major); otherwise workgroup b writes its R to rows b*n..b*n+n-1 of
  * `out` (column-major, ld_out >= workgroups * n).  FIGARO_EINVAL when the

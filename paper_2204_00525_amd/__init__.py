@@ -86,6 +86,7 @@ def lib():
         "figaro_debug_stack": (i32, [vp, pp, pi64, vp, vp]),
         "figaro_debug_stack_layout": (i32, [vp, pi64, i32]),
         "figaro_debug_tile_rows": (i64, [i32, i32]),
+        "figaro_debug_dense_rows": (i64, [i32, i32, i64]),
         "figaro_batch_create": (i32, [ctypes.POINTER(vp), i32, ctypes.POINTER(vp), i32]),
         "figaro_batch_destroy": (None, [vp]),
         "figaro_batch_stream_of": (i32, [vp, i32]),
@@ -500,6 +501,11 @@ def device_values(plan: Plan, inst, device="cuda") -> List:
 def debug_tile_rows(n: int, variant: int = 0) -> int:
     """Rows per register tile of one wave of the dense TSQR kernel."""
     return int(lib().figaro_debug_tile_rows(n, variant))
+
+
+def debug_dense_rows(n: int, variant: int, tiles_per_wave: int) -> int:
+    """Rows that one workgroup of the dense TSQR kernel folds."""
+    return int(lib().figaro_debug_dense_rows(n, variant, tiles_per_wave))
 
 
 def debug_dense_step(A, workgroups: int, tiles_per_wave: int, variant: int = 0, stream=None):

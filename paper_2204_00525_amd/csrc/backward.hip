@@ -17,42 +17,43 @@ namespace figaro {
 namespace {
 
 // K = R^{-1} Phi R^{-T} with Phi = tril(M) + tril(M,-1)^T, M = R triu(dR)^T.
-// One workgroup of 64 threads, n <= 64.  Thread t owns column t.
-__global__ __launch_bounds__(64) void k_qr_adjoint(const double *R, const double *dR, int n, double *K,
-                                                   int32_t *status) {
-    __shared__ double sR[64][65];
-    __shared__ double sW[64][65];
+// One workgroup of 128 threads, n <= 128; thread t owns column t.  R is
+// staged in LDS; W (global, n x n) holds Y = R^{-1} Phi between the two
+// triangular solves.
+__global__ __launch_bounds__(kMaxCols) void k_qr_adjoint(const double *R, const double *dR, int n, double *K,
+                                                         double *W, int32_t *status) {
+    __shared__ double sR[kMaxCols][kMaxCols + 1];
     const int t = threadIdx.x;
     if (t < n)
         for (int c = 0; c < n; ++c) sR[t][c] = (c >= t) ? R[(int64_t)c * n + t] : 0.0;
     __syncthreads();
-    // M[i][t] = sum_{k >= max(i, t)} R[i][k] dR[t][k]
-    if (t < n)
+    if (t < n) {
+        double *w = W + (int64_t)t * n;
+        // column t of Phi: M[i][t] for i >= t, M[t][i] for i < t, with
+        // M[i][j] = sum_{k >= max(i, j)} R[i][k] dR[j][k]
         for (int i = 0; i < n; ++i) {
+            const int a = (i >= t) ? i : t, b = (i >= t) ? t : i;
             double m = 0.0;
-            for (int k = (i > t ? i : t); k < n; ++k) m = fma(sR[i][k], dR[(int64_t)k * n + t], m);
-            sW[i][t] = m;
+            for (int k = a; k < n; ++k) m = fma(sR[a][k], dR[(int64_t)k * n + b], m);
+            w[i] = m;
         }
-    __syncthreads();
-    // symmetrise from the lower triangle: Phi[i][t] = M[t][i] for i < t
-    if (t < n)
-        for (int i = 0; i < t; ++i) sW[i][t] = sW[t][i];
-    __syncthreads();
-    // Y = R^{-1} Phi, column t in place
-    if (t < n)
+        // Y[:, t] = R^{-1} Phi[:, t]
         for (int i = n - 1; i >= 0; --i) {
-            double y = sW[i][t];
-            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], sW[k][t], y);
-            sW[i][t] = y / sR[i][i];
+            double y = w[i];
+            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], w[k], y);
+            w[i] = y / sR[i][i];
         }
+    }
     __syncthreads();
-    // K = R^{-1} Y^T: column t solves R k = (row t of Y)
-    if (t < n)
+    if (t < n) {
+        // K[:, t] = R^{-1} (row t of Y)
+        double *kt = K + (int64_t)t * n;
         for (int i = n - 1; i >= 0; --i) {
-            double y = sW[t][i];
-            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], K[(int64_t)t * n + k], y);
-            K[(int64_t)t * n + i] = y / sR[i][i];
+            double y = W[(int64_t)i * n + t];
+            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], kt[k], y);
+            kt[i] = y / sR[i][i];
         }
+    }
     if (t == 0) {
         int32_t singular = 0;
         for (int i = 0; i < n; ++i) singular |= (sR[i][i] == 0.0) ? 1 : 0;
@@ -60,11 +61,108 @@ __global__ __launch_bounds__(64) void k_qr_adjoint(const double *R, const double
     }
 }
 
+// Second half of the backward of a head/tail tile: g holds dT (the
+// gradient of the tail rows) on the output columns oc0 .. oc0 + nout - 1 of
+// the level.  w = beta dT; the suffix sums over each piece run as a forward
+// segmented scan over the lanes in reverse order; the item gradients
+//   ds_t = alpha_t dT_t - sum_{u > t in its piece} w_u + dsigma[piece of t]
+// are written to gout (column-major through the wave's LDS staging slice, or
+// row-major directly).
+template <int NB, int RPL>
+__device__ __forceinline__ void bwd_finish(const HelmertBwdArgs &a, double (&x)[RPL][NB], const TileItems<RPL> &ti,
+                                           int64_t cs, int64_t ce, int lane, int oc0, int nout, double *st) {
+    double agg[NB];
+    bool lane_last = false;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) agg[c] = 0.0;
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        // lane aggregate for the lanes below: items up to and including the
+        // lane's first piece end
+        const double wk = lane_last ? 0.0 : ti.be[k];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) agg[c] = fma(wk, x[k][c], agg[c]);
+        lane_last = lane_last || ti.last[k];
+    }
+    const int rev = 63 - lane;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) agg[c] = __shfl(agg[c], rev, 64);
+    segmented_carry<NB>(agg, __builtin_bitreverse64(__ballot(lane_last)), lane);
+    double run[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) run[c] = __shfl(agg[c], rev, 64);
+#pragma unroll
+    for (int k = RPL - 1; k >= 0; --k) {
+        const double lm = ti.last[k] ? 0.0 : 1.0;
+        const int32_t pk = ti.valid[k] ? ti.pid[k] : 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const double E = run[c] * lm;
+            const double gp = (c < nout) ? a.gpieces[(int64_t)(oc0 + c) * a.ld_gp + pk] : 0.0;
+            const double out = fma(ti.al[k], x[k][c], -E) + gp;
+            run[c] = fma(ti.be[k], x[k][c], E);
+            x[k][c] = out;
+        }
+    }
+    const int64_t nitems = ce - cs;
+    if (a.gout_rowmajor) {
+        // rows of the lane's items are contiguous in a row-major output
+        const int64_t base = cs + (int64_t)lane * RPL;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k)
+            if (ti.valid[k]) {
+                double *row = a.gout + (base + k) * a.ld_gout + oc0;
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    if (c < nout) row[c] = x[k][c];
+            }
+        return;
+    }
+    // coalesced stores: per column, the lane-contiguous items go through the
+    // wave's LDS slice and come back lane-strided (same wave: LDS accesses
+    // complete in order, no barrier needed)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        // (a guard, not a break: a break would stop the unrolling and send x
+        // to scratch memory)
+        if (c < nout) {
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) st[lane * RPL + k] = x[k][c];
+            double v[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) v[k] = st[k * 64 + lane];
+            double *dst = a.gout + (int64_t)(oc0 + c) * a.ld_gout + cs;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (k * 64 + lane < nitems) dst[k * 64 + lane] = v[k];
+        }
+    }
+}
+
+// g[k][c] += sum_e x[k][e] * sK[koff + e * NB + c], two rows at a time (each
+// K row read serves both).
+template <int NB, int RPL>
+__device__ __forceinline__ void tile_times_k(const double (&x)[RPL][NB], const double *sK, int koff,
+                                             double (&g)[RPL][NB]) {
+    constexpr int KB = (RPL % 2 == 0) ? 2 : 1;
+#pragma unroll
+    for (int k0 = 0; k0 < RPL; k0 += KB) {
+#pragma unroll
+        for (int e = 0; e < NB; ++e) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const double kv = sK[koff + e * NB + c];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) g[k0 + q][c] = fma(x[k0 + q][e], kv, g[k0 + q][c]);
+            }
+        }
+    }
+}
+
 // Backward of one head/tail level; see HelmertBwdArgs.  Chunks are
 // independent here (no accumulation), one or more per wave.  The block of K
 // that the level's rows touch is staged in LDS; the tails are recomputed
-// (tile_tails) and replaced by dT = T K_blk; the suffix sums over each piece
-// run as a forward segmented scan over the lanes in reverse order.
+// (tile_tails) and dT = T K_blk goes through bwd_finish.
 template <int NB, int RPL, int MODE>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
     __shared__ double sK[NB * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[c]], zero outside ncols
@@ -79,107 +177,67 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
     if (wave >= a.waves) return;
     const int64_t c_begin = a.nchunks * wave / a.waves;
     const int64_t c_end = a.nchunks * (wave + 1) / a.waves;
+    double *st = stage + (threadIdx.x >> 6) * (64 * RPL);
     for (int64_t ch = c_begin; ch < c_end; ++ch) {
         const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
         double x[RPL][NB];
         TileItems<RPL> ti;
-        tile_tails<NB, RPL, MODE, false>(a, cs, ce, lane, x, ti);
-        // dT = T K_blk, two rows at a time (each K row read serves both).  The
-        // LDS offset is opaque to the compiler, so the reads of K are not
+        tile_tails<NB, RPL, MODE, false>(tail_src(a), cs, ce, lane, x, ti);
+        // The LDS offset is opaque to the compiler, so the reads of K are not
         // hoisted out of the chunk loop (all of K would not fit in registers).
         int koff = 0;
         asm volatile("" : "+v"(koff));
-        constexpr int KB = (RPL % 2 == 0) ? 2 : 1;
+        double g[RPL][NB];
 #pragma unroll
-        for (int k0 = 0; k0 < RPL; k0 += KB) {
-            double t[KB][NB];
+        for (int k = 0; k < RPL; ++k)
 #pragma unroll
-            for (int q = 0; q < KB; ++q)
+            for (int c = 0; c < NB; ++c) g[k][c] = 0.0;
+        tile_times_k<NB, RPL>(x, sK, koff, g);
+        bwd_finish<NB, RPL>(a, g, ti, cs, ce, lane, 0, a.ncols, st);
+    }
+}
+
+// The same for wide levels (ncols > kChunkCols), in column chunks of
+// kChunkCols: workgroup column blockIdx.y produces the gradient on output
+// columns oc0 .. oc0 + 31; for every input chunk the tails are recomputed
+// and multiplied by the matching block of K (all of K[:, oc0..] is staged).
+template <int MODE>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd_wide(HelmertBwdArgs a) {
+    constexpr int NB = kChunkCols, RPL = 2;
+    __shared__ double sK[kMaxCols * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[oc0 + c]]
+    __shared__ double stage[kWavesPerBlock * 64 * RPL];
+    const int oc0 = blockIdx.y * NB;
+    const int nout = min(NB, a.ncols - oc0);
+    for (int i = threadIdx.x; i < kMaxCols * NB; i += blockDim.x) {
+        const int e = i / NB, c = i % NB;
+        sK[i] = (e < a.ncols && c < nout) ? a.K[(int64_t)a.colmap[oc0 + c] * a.n_total + a.colmap[e]] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wave >= a.waves) return;
+    const int64_t c_begin = a.nchunks * wave / a.waves;
+    const int64_t c_end = a.nchunks * (wave + 1) / a.waves;
+    double *st = stage + (threadIdx.x >> 6) * (64 * RPL);
+    for (int64_t ch = c_begin; ch < c_end; ++ch) {
+        const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
+        double g[RPL][NB];
 #pragma unroll
-                for (int c = 0; c < NB; ++c) t[q][c] = 0.0;
+        for (int k = 0; k < RPL; ++k)
 #pragma unroll
-            for (int e = 0; e < NB; ++e) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const double kv = sK[koff + e * NB + c];
-#pragma unroll
-                    for (int q = 0; q < KB; ++q) t[q][c] = fma(x[k0 + q][e], kv, t[q][c]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < KB; ++q)
-#pragma unroll
-                for (int c = 0; c < NB; ++c) x[k0 + q][c] = t[q][c];
+            for (int c = 0; c < NB; ++c) g[k][c] = 0.0;
+        TileItems<RPL> ti;
+        for (int ic0 = 0; ic0 < a.ncols; ic0 += NB) {
+            TailSrc src = tail_src(a);
+            src.in = a.in + (int64_t)ic0 * a.ld_in;
+            src.ncols = min(NB, a.ncols - ic0);
+            double x[RPL][NB];
+            tile_tails<NB, RPL, MODE, false>(src, cs, ce, lane, x, ti);
+            int koff = ic0 * NB;
+            asm volatile("" : "+v"(koff));
+            tile_times_k<NB, RPL>(x, sK, koff, g);
         }
-        // w = beta dT.  Lane aggregate for the lanes below: the items up to
-        // and including the lane's first piece end.
-        double agg[NB];
-        bool lane_last = false;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) agg[c] = 0.0;
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            const double wk = lane_last ? 0.0 : ti.be[k];
-#pragma unroll
-            for (int c = 0; c < NB; ++c) agg[c] = fma(wk, x[k][c], agg[c]);
-            lane_last = lane_last || ti.last[k];
-        }
-        // suffix scan over the lanes: reverse the lanes, forward segmented
-        // scan (a segment starts at every lane holding a piece end), reverse
-        const int rev = 63 - lane;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) agg[c] = __shfl(agg[c], rev, 64);
-        segmented_carry<NB>(agg, __builtin_bitreverse64(__ballot(lane_last)), lane);
-        double run[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) run[c] = __shfl(agg[c], rev, 64);
-#pragma unroll
-        for (int k = RPL - 1; k >= 0; --k) {
-            const double lm = ti.last[k] ? 0.0 : 1.0;
-            const int32_t pk = ti.valid[k] ? ti.pid[k] : 0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const double E = run[c] * lm;
-                const double gp = (c < a.ncols) ? a.gpieces[(int64_t)c * a.ld_gp + pk] : 0.0;
-                const double out = fma(ti.al[k], x[k][c], -E) + gp;
-                run[c] = fma(ti.be[k], x[k][c], E);
-                x[k][c] = out;
-            }
-        }
-        const int64_t nitems = ce - cs;
-        if (a.gout_rowmajor) {
-            // rows of the lane's items are contiguous in a row-major output
-            const int64_t base = cs + (int64_t)lane * RPL;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k)
-                if (ti.valid[k]) {
-                    double *row = a.gout + (base + k) * a.ld_gout;
-#pragma unroll
-                    for (int c = 0; c < NB; ++c)
-                        if (c < a.ncols) row[c] = x[k][c];
-                }
-            continue;
-        }
-        // coalesced stores: per column, the lane-contiguous items go through
-        // the wave's LDS slice and come back lane-strided (same wave: LDS
-        // accesses complete in order, no barrier needed)
-        double *st = stage + (threadIdx.x >> 6) * (64 * RPL);
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            // (a guard, not a break: a break would stop the unrolling and
-            // send x to scratch memory)
-            if (c < a.ncols) {
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) st[lane * RPL + k] = x[k][c];
-                double v[RPL];
-#pragma unroll
-                for (int k = 0; k < RPL; ++k) v[k] = st[k * 64 + lane];
-                double *dst = a.gout + (int64_t)c * a.ld_gout + cs;
-#pragma unroll
-                for (int k = 0; k < RPL; ++k)
-                    if (k * 64 + lane < nitems) dst[k * 64 + lane] = v[k];
-            }
-        }
+        bwd_finish<NB, RPL>(a, g, ti, cs, ce, lane, oc0, nout, st);
     }
 }
 
@@ -244,34 +302,41 @@ __global__ void k_copy_cols(const double *src, int64_t ld_src, double *dst, int6
 int nb_bwd(int ncols) {
     if (ncols <= 8) return 8;
     if (ncols <= 16) return 16;
-    if (ncols <= 32) return 32;
-    return 64;
+    return 32;
 }
 
 template <int NB>
 hipError_t helmert_bwd_nb(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
-    constexpr int RPL = (NB == 8) ? 8 : (NB == 16 ? 4 : (NB == 32 ? 2 : 1));
+    constexpr int RPL = (NB == 8) ? 8 : (NB == 16 ? 4 : 2);
     dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock), block(64 * kWavesPerBlock);
     if (unit) hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 0>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 1>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
+hipError_t helmert_bwd_wide(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
+    dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock, (a.ncols + kChunkCols - 1) / kChunkCols);
+    dim3 block(64 * kWavesPerBlock);
+    if (unit) hipLaunchKernelGGL((k_helmert_bwd_wide<0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_helmert_bwd_wide<1>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, int32_t *status,
+hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, double *W, int32_t *status,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(64), 0, s, R, dR, (int)n, K, status);
+    hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(kMaxCols), 0, s, R, dR, (int)n, K, W, status);
     return hipGetLastError();
 }
 
 hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
     if (a.waves <= 0 || a.nchunks <= 0) return hipSuccess;
+    if (a.ncols > kChunkCols) return helmert_bwd_wide(a, unit, s);
     switch (nb_bwd(a.ncols)) {
         case 8: return helmert_bwd_nb<8>(a, unit, s);
         case 16: return helmert_bwd_nb<16>(a, unit, s);
-        case 32: return helmert_bwd_nb<32>(a, unit, s);
-        default: return helmert_bwd_nb<64>(a, unit, s);
+        default: return helmert_bwd_nb<32>(a, unit, s);
     }
 }
 

@@ -13,7 +13,12 @@
 namespace figaro {
 
 // Widest column count the register-tile kernels handle.
-constexpr int kMaxCols = 64;
+constexpr int kMaxCols = 128;
+// Head/tail tasks with more columns than this write their tails to the stack
+// of the post-processing TSQR, in column chunks of kChunkCols, instead of
+// folding them into a register-tile QR.
+constexpr int kFusedMaxCols = 40;
+constexpr int kChunkCols = 32;
 
 // ---------------------------------------------------------------------------
 // Kernel argument blocks (passed by value).
@@ -51,8 +56,8 @@ struct HelmertArgs {
     int64_t ld_stack;
     int64_t stack_row0;
     int32_t n_total;
-    uint64_t other_cols;         // bit g set: global column g is not a column of this block
-    int8_t colmap[kMaxCols];     // global column of every local column
+    uint64_t other_cols[2];      // bit g set: global column g is not a column of this block
+    uint8_t colmap[kMaxCols];    // global column of every local column
     // R0 output (materialisation for inspection)
     double *r0;
     int64_t ld_r0;
@@ -95,7 +100,7 @@ struct HelmertBwdArgs {
     int64_t nchunks;
     const double *K;             // n_total x n_total, column-major
     int32_t n_total;
-    int8_t colmap[64];
+    uint8_t colmap[kMaxCols];
     const double *gpieces;       // gradient of the piece sums, [ncols][ld_gp]
     int64_t ld_gp;
     double *gout;                // gradient of the items, [ncols][ld_gout] (or [items][ld_gout])
@@ -193,7 +198,7 @@ hipError_t launch_permute(const double *src, int64_t ld_src, double *dst, int64_
                           const int64_t *perm, int64_t rows, int32_t ncols, bool inverse,
                           int64_t total_rows, hipStream_t s);
 hipError_t launch_fill(double *p, int64_t count, double v, hipStream_t s);
-hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, int32_t *status,
+hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, double *W, int32_t *status,
                              hipStream_t s);
 hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s);
 hipError_t launch_join_bwd(const JoinBwdArgs &a, hipStream_t s);
@@ -210,6 +215,7 @@ figaro_status run_backward(figaro_plan_s *p, const double *const *values, const 
 int tile_items_for(int ncols, int variant);   // items per chunk of the register-tile kernel
 int num_variants();                           // number of register-tile kernel variants
 int dense_tile_rows_for(int ncols, int variant);   // rows per tile of the dense kernel
+int dense_waves_per_block(int ncols);   // waves of a workgroup that fold separate tiles
 int waves_per_block();                // waves per workgroup of the QR kernels
 
 // ---------------------------------------------------------------------------
@@ -323,6 +329,7 @@ struct figaro_plan_s {
     std::vector<figaro::DenseLevel> dense;
     int64_t r0_rows = 0;
     double *d_K = nullptr;           // n x n, backward
+    double *d_W = nullptr;           // n x n scratch of the QR adjoint
     int32_t *d_status = nullptr;     // device status word of the backward pass
     int64_t workspace_bytes = 0;
     std::vector<void *> allocations;

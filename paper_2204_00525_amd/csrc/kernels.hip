@@ -272,8 +272,9 @@ __device__ __forceinline__ void store_r(const HelmertArgs &a, const double *rw, 
 #pragma unroll
     for (int c = 0; c < NB; ++c)
         if (c < a.ncols) a.stack[(int64_t)a.colmap[c] * a.ld_stack + row] = rw[lane * NB + c];
-    for (uint64_t m = a.other_cols; m; m &= m - 1)
-        a.stack[(int64_t)__builtin_ctzll(m) * a.ld_stack + row] = 0.0;
+    for (int h = 0; h < 2; ++h)
+        for (uint64_t m = a.other_cols[h]; m; m &= m - 1)
+            a.stack[(int64_t)(64 * h + __builtin_ctzll(m)) * a.ld_stack + row] = 0.0;
 }
 
 // MODE 0: items count 1 each (tail coefficients from the position in the
@@ -310,7 +311,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
             const int64_t ch = c_begin + it;
             const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
             TileItems<RPL> ti;
-            tile_tails<NB, RPL, MODE, true>(a, cs, ce, lane, x, ti);
+            TailSrc src = tail_src(a);
+            src.pieces_out = a.pieces_out;
+            src.ld_pieces = a.ld_pieces;
+            tile_tails<NB, RPL, MODE, true>(src, cs, ce, lane, x, ti);
             if constexpr (!FUSE) {
                 const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
@@ -320,8 +324,9 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
 #pragma unroll
                     for (int c = 0; c < NB; ++c)
                         if (c < a.ncols) a.r0[(int64_t)a.colmap[c] * a.ld_r0 + row] = x[k][c];
-                    for (uint64_t m = a.other_cols; m; m &= m - 1)
-                        a.r0[(int64_t)__builtin_ctzll(m) * a.ld_r0 + row] = 0.0;
+                    for (int h = 0; h < 2; ++h)
+                        for (uint64_t m = a.other_cols[h]; m; m &= m - 1)
+                            a.r0[(int64_t)(64 * h + __builtin_ctzll(m)) * a.ld_r0 + row] = 0.0;
                     if (a.block_of_row) a.block_of_row[row] = a.block_id;
                 }
                 continue;
@@ -385,6 +390,130 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
     }
 }
 
+// Dense TSQR step for wide matrices (kFusedMaxCols < n <= kMaxCols): the W
+// waves of a workgroup share each tile of kWideRows rows; wave w holds
+// columns [32w, 32w + 32) of the tile (kWideRPL rows per lane) and the same
+// columns of the workgroup's R (all n rows, row-major, in its LDS slice).
+// At the step of column j the wave that owns j forms the reflector from its
+// own column (kept at register column 0 by rotating its columns) and
+// publishes the column and the reflector's scalars through LDS; after one
+// barrier the waves to its right apply the reflector to their columns (and
+// their part of row j of R).  The scalars and the column are double-buffered,
+// so one barrier per column suffices.  Every wave runs the same number of
+// steps and barriers.  Workgroup b folds rows [b W', (b+1) W'), W' =
+// tiles_per_wave * kWideRows, into one R; the single workgroup of the last
+// level sign-normalises it.
+constexpr int kWideCols = 32;
+constexpr int kWideRPL = 2;
+constexpr int kWideRows = 64 * kWideRPL;
+
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_dense_wide(DenseArgs a) {
+    constexpr int CW = kWideCols, RPL = kWideRPL, T = kWideRows;
+    constexpr int NW = CW * W;                   // rows of an R slice
+    constexpr int SL = (NW + 1) * CW;            // slice: NW rows + a spare row
+    __shared__ double rsl[W * SL];
+    __shared__ double xb[2][T];
+    __shared__ double sc[2][4];
+    const int lane = threadIdx.x & 63;
+    const int wib = threadIdx.x >> 6;
+    double *rw = rsl + wib * SL;
+    for (int i = lane; i < SL; i += 64) rw[i] = 0.0;
+    const int n = a.n;
+    for (int64_t it = 0; it < a.tiles_per_wave; ++it) {
+        double x[RPL][CW];
+        const int64_t base = ((int64_t)blockIdx.x * a.tiles_per_wave + it) * T + (int64_t)lane * RPL;
+#pragma unroll
+        for (int c = 0; c < CW; ++c) {
+            const int col = CW * wib + c;
+            const bool live = col < n;
+            const double *src = a.in + (int64_t)(live ? col : 0) * a.ld_in;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? src[base + k] : 0.0;
+        }
+        for (int j = 0; j < n; ++j) {
+            const int o = j / CW, jl = j - o * CW, slot = j & 1;
+            if (wib == o) {
+                // register column k holds local column jl + k
+                double d[CW], p[CW];
+#pragma unroll
+                for (int k = 0; k < CW; ++k) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) acc = fma(x[r][0], x[r][k], acc);
+                    d[k] = acc;
+                }
+#pragma unroll
+                for (int k = 0; k < CW; ++k) {
+                    const bool in_row = k < CW - jl;
+                    const double v = rw[in_row ? j * CW + jl + k : NW * CW + k];
+                    p[k] = in_row ? v : 0.0;
+                }
+                wave_sum_batch<CW>(d);
+                const Reflector h = reflector(p[0], d[0]);
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) xb[slot][lane * RPL + r] = x[r][0];
+                sc[slot][0] = h.scale;
+                sc[slot][1] = h.ts;
+                sc[slot][2] = h.tau;
+#pragma unroll
+                for (int k = 1; k < CW; ++k) {
+                    const double w = fma(h.scale, d[k], p[k]);
+                    const double g = h.ts * w;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][0], x[r][k]);
+                    rw[(k < CW - jl) ? j * CW + jl + k : NW * CW + k] = fma(-h.tau, w, p[k]);
+                }
+                rw[j * CW + jl] = h.rjj;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+                    for (int k = 0; k < CW - 1; ++k) x[r][k] = x[r][k + 1];
+                    x[r][CW - 1] = 0.0;
+                }
+            }
+            __syncthreads();
+            if (wib > o) {
+                double xj[RPL], d[CW], p[CW];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) xj[r] = xb[slot][lane * RPL + r];
+                const double scale = sc[slot][0], ts = sc[slot][1], tau = sc[slot][2];
+#pragma unroll
+                for (int k = 0; k < CW; ++k) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) acc = fma(xj[r], x[r][k], acc);
+                    d[k] = acc;
+                    p[k] = rw[j * CW + k];
+                }
+                wave_sum_batch<CW>(d);
+#pragma unroll
+                for (int k = 0; k < CW; ++k) {
+                    const double w = fma(scale, d[k], p[k]);
+                    const double g = ts * w;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, xj[r], x[r][k]);
+                    rw[j * CW + k] = fma(-tau, w, p[k]);
+                }
+            }
+        }
+    }
+    __syncthreads();   // every slice complete (the diagonal is read across slices)
+    const bool fin = gridDim.x == 1 && a.final_r;
+    for (int j = lane; j < n; j += 64) {
+        const double dg = rsl[(j / CW) * SL + j * CW + (j % CW)];
+        const double sg = (fin && dg < 0.0) ? -1.0 : 1.0;
+#pragma unroll 4
+        for (int c = 0; c < CW; ++c) {
+            const int col = CW * wib + c;
+            if (col >= n) break;
+            const double v = (col >= j) ? sg * rw[j * CW + c] : 0.0;
+            if (fin) a.final_r[(int64_t)col * n + j] = v;
+            else a.out[(int64_t)col * a.ld_out + (int64_t)blockIdx.x * n + j] = v;
+        }
+    }
+}
+
 // One thread per (key group, output column): the column's source (own sums
 // or a child's sums gathered through the child index) times the exact
 // integer multiplier of the group.
@@ -442,8 +571,7 @@ int nb_for(int ncols) {
     if (ncols <= 8) return 8;
     if (ncols <= 16) return 16;
     if (ncols <= 32) return 32;
-    if (ncols <= 40) return 40;
-    return 64;
+    return 40;
 }
 
 // Tile shapes of the head/tail + QR kernel: rows per lane (RPL), minimum
@@ -453,9 +581,9 @@ int nb_for(int ncols) {
 // unrolled, two waves per SIMD.
 template <int NB, int V>
 struct Shape {
-    static constexpr bool ROT = V == 1 || NB > 40;
+    static constexpr bool ROT = V == 1;
     static constexpr int RPL = V == 2 ? (NB <= 8 ? 6 : NB <= 16 ? 3 : 1)
-                                      : (NB <= 8 ? 8 : NB <= 16 ? 4 : (NB <= 40 && !ROT) ? 2 : 1);
+                                      : (NB <= 8 ? 8 : NB <= 16 ? 4 : !ROT ? 2 : 1);
     static constexpr int OCC = (V == 2 && NB <= 32) ? 2 : 1;
 };
 
@@ -516,6 +644,8 @@ int tile_items_v(int ncols) {
 }
 
 int tile_items_for(int ncols, int variant) {
+    // wide tasks run in column chunks of kChunkCols
+    if (ncols > kFusedMaxCols) ncols = kChunkCols;
     switch (variant) {
         case 1: return tile_items_v<1>(ncols);
         case 2: return tile_items_v<2>(ncols);
@@ -523,7 +653,13 @@ int tile_items_for(int ncols, int variant) {
     }
 }
 
-int dense_tile_rows_for(int ncols, int variant) { return tile_items_for(ncols, variant); }
+int dense_tile_rows_for(int ncols, int variant) {
+    return ncols > kFusedMaxCols ? kWideRows : tile_items_for(ncols, variant);
+}
+
+int dense_waves_per_block(int ncols) {
+    return ncols > kFusedMaxCols ? 1 : kWavesPerBlock;
+}
 int waves_per_block() { return kWavesPerBlock; }
 int num_variants() { return kVariants; }
 
@@ -533,8 +669,10 @@ hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int varian
         case 8: return helmert_v<8>(a, unit, fuse, variant, s);
         case 16: return helmert_v<16>(a, unit, fuse, variant, s);
         case 32: return helmert_v<32>(a, unit, fuse, variant, s);
-        case 40: return variant == 1 ? helmert_nb<40, 1>(a, unit, fuse, s) : helmert_nb<40, 0>(a, unit, fuse, s);
-        default: return helmert_nb<64, 0>(a, unit, fuse, s);
+        case 40:
+            if (a.ncols > kFusedMaxCols) return hipErrorInvalidValue;   // wide tasks run in column chunks
+            return variant == 1 ? helmert_nb<40, 1>(a, unit, fuse, s) : helmert_nb<40, 0>(a, unit, fuse, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -544,8 +682,17 @@ hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
         case 8: return dense_v<8>(a, variant, s);
         case 16: return dense_v<16>(a, variant, s);
         case 32: return dense_v<32>(a, variant, s);
-        case 40: return variant == 1 ? dense_nb<40, 1>(a, s) : dense_nb<40, 0>(a, s);
-        default: return dense_nb<64, 0>(a, s);
+        default:
+            if (a.n <= kFusedMaxCols) return variant == 1 ? dense_nb<40, 1>(a, s) : dense_nb<40, 0>(a, s);
+            if (a.n > kMaxCols) return hipErrorInvalidValue;
+            {
+                const int w = (a.n + kWideCols - 1) / kWideCols;
+                dim3 grid(a.waves);
+                if (w == 2) hipLaunchKernelGGL(k_dense_wide<2>, grid, dim3(128), 0, s, a);
+                else if (w == 3) hipLaunchKernelGGL(k_dense_wide<3>, grid, dim3(192), 0, s, a);
+                else hipLaunchKernelGGL(k_dense_wide<4>, grid, dim3(256), 0, s, a);
+            }
+            return hipGetLastError();
     }
 }
 

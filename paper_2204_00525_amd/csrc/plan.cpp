@@ -340,7 +340,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         n += p->rel[i].ncols;
     }
     p->n = n;
-    if (n > kMaxCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 64 data columns in total");
+    if (n > kMaxCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 128 data columns in total");
     // ---- keys to the host
     B.keys.resize(r);
     for (int i = 0; i < r; ++i) {
@@ -681,8 +681,9 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             for (auto &L : T->levels) {
                 L.stack_row0 = srow;
                 // the first level folds its tails into one R per workgroup;
-                // the upper levels hold few rows and append their tails as is
-                if (&L == &T->levels[0])
+                // the upper levels hold few rows and append their tails as
+                // is, and so do all levels of a wide task
+                if (&L == &T->levels[0] && T->ncols <= kFusedMaxCols)
                     srow += (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols;
                 else
                     srow += L.items;
@@ -699,28 +700,34 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     }
     p->stack_rows = srow;
     p->r0_rows = r0row;
-    // dense TSQR levels over the stack: a workgroup (waves_per_block waves)
-    // folds waves_per_block * tiles_per_wave tiles into one R of n rows
+    // dense TSQR levels over the stack: a workgroup folds tiles_per_wave
+    // steps of wpb tiles (wpb waves on separate tiles; one shared tile for
+    // wide matrices) into one R of n rows, so each level divides the rows by
+    // at least 4
     const int64_t dt = dense_tile_rows_for(n, p->variant);
-    const int64_t wpb = waves_per_block();
+    const int64_t wpb = dense_waves_per_block(n);
+    const int64_t step_rows = wpb * dt;
+    const bool wide = n > kFusedMaxCols;
+    const int64_t mid_tpw = wide ? 4 : 1, final_tiles = wide ? 8 : 4;
     int64_t rows = srow;
     int64_t maxnext = 0;
     while (true) {
         DenseLevel D;
         D.rows = rows;
-        if (rows <= 4 * wpb * dt) {
+        if (rows <= final_tiles * step_rows) {
             D.waves = 1;
-            D.tiles_per_wave = std::max<int64_t>(1, (rows + wpb * dt - 1) / (wpb * dt));
+            D.tiles_per_wave = std::max<int64_t>(1, (rows + step_rows - 1) / step_rows);
             p->dense.push_back(D);
             break;
         }
-        D.tiles_per_wave = 1;
-        D.waves = (int32_t)((rows + wpb * dt - 1) / (wpb * dt));
+        D.tiles_per_wave = mid_tpw;
+        D.waves = (int32_t)((rows + mid_tpw * step_rows - 1) / (mid_tpw * step_rows));
         p->dense.push_back(D);
         rows = (int64_t)D.waves * n;
         maxnext = std::max(maxnext, rows);
     }
     if (dev_alloc(p, (void **)&p->d_K, sizeof(double) * (size_t)n * (size_t)n) != hipSuccess ||
+        dev_alloc(p, (void **)&p->d_W, sizeof(double) * (size_t)n * (size_t)n) != hipSuccess ||
         dev_alloc(p, (void **)&p->d_status, sizeof(int32_t) * 4) != hipSuccess)
         return set_error(p, FIGARO_ENOMEM, "hipMalloc");
     p->stack_ld[0] = std::max<int64_t>(srow, 1);

@@ -4,6 +4,8 @@
 // host is never synchronised.
 #include <string>
 
+#include <algorithm>
+
 #include "internal.hpp"
 #include "../../include/figaro_debug.h"
 
@@ -40,6 +42,13 @@ struct ProfScope {
             p->prof_pending.push_back({kind, slot, bytes, flops});
     }
 };
+
+// Bit g of the two words: global column g (< n) is not one of `cols`.
+void set_other_cols(uint64_t (&w)[2], int n, const std::vector<int32_t> &cols) {
+    w[0] = w[1] = 0;
+    for (int g = 0; g < n; ++g) w[g >> 6] |= 1ull << (g & 63);
+    for (int32_t c : cols) w[c >> 6] &= ~(1ull << (c & 63));
+}
 
 struct Buffers {
     // per relation: own sums (key groups) and sigma (parent groups)
@@ -85,13 +94,12 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
         a.ld_stack = p->stack_ld[0];
         a.stack_row0 = L.stack_row0;
         a.n_total = p->n;
-        a.other_cols = ~0ull >> (64 - p->n);
-        for (int c = 0; c < T.ncols; ++c) {
-            a.colmap[c] = (int8_t)T.cols[c];
-            a.other_cols &= ~(1ull << T.cols[c]);
-        }
-        // upper levels of the fused pass write their tail rows into the stack
-        const bool fold = fuse && (&L == &T.levels[0]);
+        set_other_cols(a.other_cols, p->n, T.cols);
+        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint8_t)T.cols[c];
+        // upper levels of the fused pass write their tail rows into the
+        // stack, and so do all levels of a wide task
+        const bool wide = T.ncols > kFusedMaxCols;
+        const bool fold = fuse && (&L == &T.levels[0]) && !wide;
         const bool to_stack = fuse && !fold;
         a.r0 = to_stack ? p->d_stack[0] : r0;
         a.ld_r0 = to_stack ? p->stack_ld[0] : ld_r0;
@@ -105,7 +113,22 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
             const double bytes = 8.0 * (double)L.items * T.ncols;
             const double flops = fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
             ProfScope ps(p, s, kind, bytes, flops);
-            FIGARO_TRY(launch_helmert(a, L.unit, fold, T.variant, s));
+            if (!wide) {
+                FIGARO_TRY(launch_helmert(a, L.unit, fold, T.variant, s));
+            } else {
+                // column chunks: the tails of every column depend on that
+                // column only; the first chunk also writes the zeros of the
+                // columns outside the task
+                for (int c0 = 0; c0 < T.ncols; c0 += kChunkCols) {
+                    HelmertArgs ac = a;
+                    ac.in = cur + (int64_t)c0 * ld;
+                    ac.ncols = std::min(kChunkCols, T.ncols - c0);
+                    ac.pieces_out = L.d_pieces + (int64_t)c0 * L.npieces;
+                    for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint8_t)T.cols[c0 + c];
+                    if (c0 > 0) ac.other_cols[0] = ac.other_cols[1] = 0;
+                    FIGARO_TRY(launch_helmert(ac, L.unit, false, T.variant, s));
+                }
+            }
         }
         cur = L.d_pieces;
         ld = L.npieces;
@@ -267,7 +290,7 @@ figaro_status run_task_bwd(figaro_plan_s *p, Task &T, const double *in, int64_t 
         a.nchunks = L.nchunks;
         a.K = p->d_K;
         a.n_total = p->n;
-        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (int8_t)T.cols[c];
+        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint8_t)T.cols[c];
         a.gpieces = L.d_gpieces;
         a.ld_gp = L.npieces;
         a.gout = (l == 0) ? out.p : T.levels[l - 1].d_gpieces;
@@ -288,7 +311,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
     if (st != FIGARO_OK) return st;
     {
         ProfScope ps(p, s, 6, 0.0, 0.0);
-        FIGARO_TRY(launch_qr_adjoint(R, dR, p->n, p->d_K, p->d_status, s));
+        FIGARO_TRY(launch_qr_adjoint(R, dR, p->n, p->d_K, p->d_W, p->d_status, s));
     }
     for (auto it = p->post.rbegin(); it != p->post.rend(); ++it) {   // parents before children
         const int v = *it;
@@ -451,13 +474,18 @@ int64_t figaro_debug_tile_rows(int32_t n, int32_t variant) {
     return dense_tile_rows_for(n, variant);
 }
 
+int64_t figaro_debug_dense_rows(int32_t n, int32_t variant, int64_t tiles_per_wave) {
+    if (n < 1 || n > kMaxCols || variant < 0 || variant >= num_variants() || tiles_per_wave < 1) return -1;
+    return (int64_t)dense_waves_per_block(n) * tiles_per_wave * dense_tile_rows_for(n, variant);
+}
+
 figaro_status figaro_debug_dense_step(int32_t n, int64_t rows, const double *in, int64_t ld_in, int32_t workgroups,
                                       int64_t tiles_per_wave, int32_t variant, double *out, int64_t ld_out,
                                       double *final_r, hipStream_t stream) {
     if (n < 1 || n > kMaxCols || rows < 0 || !in || ld_in < rows || workgroups < 1 || tiles_per_wave < 1 ||
         variant < 0 || variant >= num_variants())
         return set_error(nullptr, FIGARO_EINVAL, "bad argument");
-    const int64_t per_wg = (int64_t)waves_per_block() * tiles_per_wave * dense_tile_rows_for(n, variant);
+    const int64_t per_wg = (int64_t)dense_waves_per_block(n) * tiles_per_wave * dense_tile_rows_for(n, variant);
     if ((int64_t)workgroups * per_wg < rows) return set_error(nullptr, FIGARO_EINVAL, "workgroups do not cover the rows");
     const bool fin = workgroups == 1 && final_r;
     if (!fin && (!out || ld_out < (int64_t)workgroups * n)) return set_error(nullptr, FIGARO_EINVAL, "bad output");
@@ -484,7 +512,8 @@ int32_t figaro_debug_stack_layout(figaro_plan_t p, int64_t *out, int32_t max_reg
             if (!T->active) continue;
             for (size_t l = 0; l < T->levels.size(); ++l) {
                 const Level &L = T->levels[l];
-                const int64_t rows = (l == 0) ? (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols
+                const int64_t rows = (l == 0 && T->ncols <= kFusedMaxCols)
+                                         ? (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols
                                               : L.items;
                 if (k < max_regions) {
                     out[3 * k] = T->block_id;

@@ -18,6 +18,37 @@
 namespace figaro {
 namespace {
 
+// Where the items of a head/tail level come from (a block of columns of
+// `in`), their piece ids and tail coefficients, and where piece sums go.
+struct TailSrc {
+    const double *in;
+    int64_t ld_in;
+    int32_t ncols;
+    const int32_t *pid;
+    const int64_t *piece_start;
+    const double *phi_piece;
+    const double *alpha;
+    const double *beta;
+    double *pieces_out;          // may be null
+    int64_t ld_pieces;
+};
+
+template <class Args>
+__device__ __forceinline__ TailSrc tail_src(const Args &a) {
+    TailSrc t;
+    t.in = a.in;
+    t.ld_in = a.ld_in;
+    t.ncols = a.ncols;
+    t.pid = a.pid;
+    t.piece_start = a.piece_start;
+    t.phi_piece = a.phi_piece;
+    t.alpha = a.alpha;
+    t.beta = a.beta;
+    t.pieces_out = nullptr;
+    t.ld_pieces = 0;
+    return t;
+}
+
 template <int RPL>
 struct TileItems {
     int32_t pid[RPL];
@@ -30,15 +61,15 @@ struct TileItems {
 // Loads the tile's columns into x (zero for invalid items and columns >=
 // ncols) and replaces them by the tail rows (zero for the first item of
 // every piece).  With PIECES, the sum of every piece is written to
-// pieces_out[c * ld_pieces + piece id] (Args must provide them).
+// pieces_out[c * ld_pieces + piece id] (if pieces_out is not null).
 //
 // Running sums are reset at piece starts by multiplying with a 0/1 factor
 // rather than by selects; a non-finite value therefore spreads into the
 // following pieces of the tile, which only matters for inputs that make R
 // non-finite anyway.
-template <int NB, int RPL, int MODE, bool PIECES, class Args>
-__device__ __forceinline__ void tile_tails(const Args &a, int64_t cs, int64_t ce, int lane, double (&x)[RPL][NB],
-                                           TileItems<RPL> &ti) {
+template <int NB, int RPL, int MODE, bool PIECES>
+__device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t ce, int lane,
+                                           double (&x)[RPL][NB], TileItems<RPL> &ti) {
     const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {

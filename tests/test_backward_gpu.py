@@ -54,6 +54,10 @@ CASES = {
     "two_rel_zipf": lambda: synth.two_relation(10, 3000, 3000, 6, 5, 60, dist="zipf"),
     "config4_div1000": lambda: synth.config3(seed=1004, div=1000),
     "cartesian": lambda: synth.cartesian_uniform(8, 60, 3, 50, 2),
+    # wide blocks: a 48-column project-away task (column chunks), n = 64
+    # and n = 100 (cooperative dense TSQR, QR adjoint beyond 64 columns)
+    "chain4_wide": lambda: synth.random_chain(16, 4, 40, 16, 8),
+    "star_wide_dimroot": lambda: synth.random_star(17, 5, 300, 30, 20, root=3),
 }
 
 

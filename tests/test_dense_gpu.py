@@ -21,12 +21,11 @@ def _relf(a, b):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2])
-@pytest.mark.parametrize("n", [1, 5, 8, 13, 16, 24, 32, 40, 64])
+@pytest.mark.parametrize("n", [1, 5, 8, 13, 16, 24, 32, 40, 41, 64, 65, 100, 128])
 def test_single_workgroup_matches_householder(F, oracle_lib, n, variant):
     import torch
-    tile = F.debug_tile_rows(n, variant)
     tpw = 2
-    rows = 4 * tpw * tile - 37          # several tiles and a ragged tail
+    rows = F.debug_dense_rows(n, variant, tpw) - 37     # several tiles and a ragged tail
     rng = np.random.default_rng(100 + n)
     A = rng.standard_normal((rows, n)) * 10.0 ** rng.uniform(-3, 3, n)
     R = F.debug_dense_step(torch.as_tensor(A).cuda(), 1, tpw, variant).cpu().numpy()
@@ -36,12 +35,11 @@ def test_single_workgroup_matches_householder(F, oracle_lib, n, variant):
     assert _relf(R, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [7, 16, 32, 48])
+@pytest.mark.parametrize("n", [7, 16, 32, 48, 96, 128])
 def test_many_workgroups_preserve_gram(F, oracle_lib, n):
     import torch
-    tile = F.debug_tile_rows(n, 0)
     wg = 9
-    rows = wg * 4 * tile - 5
+    rows = wg * F.debug_dense_rows(n, 0, 1) - 5
     rng = np.random.default_rng(7 + n)
     A = rng.standard_normal((rows, n))
     S = F.debug_dense_step(torch.as_tensor(A).cuda(), wg, 1, 0).cpu().numpy()
@@ -66,7 +64,6 @@ def test_rank_deficient_and_zero_columns(F, oracle_lib):
 
 def test_coverage_is_checked(F):
     import torch
-    tile = F.debug_tile_rows(16, 0)
-    A = torch.zeros((4 * tile + 1, 16), dtype=torch.float64, device="cuda")
+    A = torch.zeros((F.debug_dense_rows(16, 0, 1) + 1, 16), dtype=torch.float64, device="cuda")
     with pytest.raises(F.FigaroError):
         F.debug_dense_step(A, 1, 1, 0)

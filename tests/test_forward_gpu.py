@@ -60,6 +60,12 @@ CASES = {
     "two_rel_zipf": lambda: synth.two_relation(10, 20000, 20000, 16, 16, 200, dist="zipf"),
     "two_rel_int64": lambda: synth.two_relation(11, 3000, 2000, 3, 4, 50, key_dtype=np.int64),
     "wide_root_40": lambda: synth.random_star(12, 5, 4000, 80, 8),
+    # more than 40 columns: wide head/tail tasks in column chunks, the
+    # cooperative dense TSQR (two, three and four column groups)
+    "chain4_wide_64": lambda: synth.random_chain(16, 4, 120, 16, 12),
+    "star_wide_dimroot_100": lambda: synth.random_star(17, 5, 1500, 40, 20, root=3),
+    "star_wide_fact_root_90": lambda: synth.random_star(18, 3, 2000, 60, 30),
+    "chain4_wide_128": lambda: synth.random_chain(19, 4, 60, 32, 10),
 }
 
 
@@ -77,7 +83,8 @@ def test_forward_matches_oracle(F, oracle_lib, name):
 
 
 @pytest.mark.parametrize("tile", [64, 128])
-@pytest.mark.parametrize("name", ["two_rel_zipf", "config3_div1000", "chain4_zipf", "paper_fig3_b"])
+@pytest.mark.parametrize("name", ["two_rel_zipf", "config3_div1000", "chain4_zipf", "paper_fig3_b",
+                                  "star_wide_dimroot_100"])
 def test_forward_small_tiles_split_groups(F, oracle_lib, name, tile):
     """Small tiles split key groups across tiles and need several levels of
     the piece combination; R must not change."""
@@ -157,7 +164,7 @@ def test_config2_full_counts_and_sampled_r(F, oracle_lib):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("name", ["config1", "paper_fig3_b", "chain3", "star_nonpk", "config3_div1000",
-                                  "two_rel_zipf", "star_pk"])
+                                  "two_rel_zipf", "star_pk", "chain4_wide_64"])
 @pytest.mark.parametrize("tile", [0, 64, 128])
 def test_r0_theorem6(F, oracle_lib, name, tile):
     import torch
@@ -236,7 +243,8 @@ def test_counts_match_definitions(F, oracle_lib, maker):
 
 
 @pytest.mark.parametrize("name", ["config1", "config2_div1000", "config3_div1000", "two_rel_zipf", "chain4_zipf",
-                                  "star_nonpk", "paper_fig3_b", "star_dim_root"])
+                                  "star_nonpk", "paper_fig3_b", "star_dim_root", "chain4_wide_64",
+                                  "star_wide_dimroot_100"])
 @pytest.mark.parametrize("tile", [0, 64])
 @pytest.mark.parametrize("variant", [1, 2])
 def test_forward_variants(F, oracle_lib, name, tile, variant):
