@@ -17,6 +17,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -113,6 +116,59 @@ struct Builder {
             v |= (u128)(uint32_t)ids[i][(size_t)kp * p->rel[i].m_in + row] << pk.shift[q];
         }
         return v;
+    }
+    // packed keys of every row of relation i
+    std::vector<u128> pack_all(int i, const Packer &pk) const {
+        const int64_t m = p->rel[i].m_in;
+        std::vector<u128> v(m, 0);
+        for (size_t q = 0; q < pk.attrs.size(); ++q) {
+            const int32_t *col = ids[i].data() + (size_t)key_pos(i, pk.attrs[q]) * m;
+            const int sh = pk.shift[q];
+            for (int64_t t = 0; t < m; ++t) v[t] |= (u128)(uint32_t)col[t] << sh;
+        }
+        return v;
+    }
+};
+
+// Sorts 128-bit words whose set bits all lie below `bits`: least significant
+// digit first radix sort, 16-bit digits (stable passes, so equal digits keep
+// their order).
+void radix_sort_u128(std::vector<u128> &v, int bits) {
+    if (v.size() < 2) return;
+    std::vector<u128> tmp(v.size());
+    std::vector<int64_t> count(1 << 16);
+    for (int shift = 0; shift < bits; shift += 16) {
+        std::fill(count.begin(), count.end(), 0);
+        for (u128 x : v) ++count[(size_t)(x >> shift) & 0xffff];
+        int64_t sum = 0;
+        for (auto &c : count) {
+            const int64_t t = c;
+            c = sum;
+            sum += t;
+        }
+        for (u128 x : v) tmp[count[(size_t)(x >> shift) & 0xffff]++] = x;
+        v.swap(tmp);
+    }
+}
+
+// Position of packed keys in a sorted list of distinct keys: a direct table
+// when the keys have few bits, else binary search.
+struct KeyIndex {
+    static constexpr int kDirectBits = 26;
+    bool direct = false;
+    std::vector<int32_t> table;         // direct: key -> position, -1 absent
+    const std::vector<u128> *sorted = nullptr;
+    KeyIndex(const std::vector<u128> &keys, int bits) : sorted(&keys) {
+        if (bits <= kDirectBits) {
+            direct = true;
+            table.assign((size_t)1 << bits, -1);
+            for (size_t q = 0; q < keys.size(); ++q) table[(size_t)keys[q]] = (int32_t)q;
+        }
+    }
+    int64_t find(u128 k) const {
+        if (direct) return table[(size_t)k];
+        auto it = std::lower_bound(sorted->begin(), sorted->end(), k);
+        return (it == sorted->end() || *it != k) ? -1 : (int64_t)(it - sorted->begin());
     }
 };
 
@@ -245,8 +301,22 @@ figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total) {
     return FIGARO_OK;
 }
 
+// Phase timing of plan construction, printed to stderr when the environment
+// variable FIGARO_PLAN_TIMING is set.
+struct PhaseTimer {
+    bool on = std::getenv("FIGARO_PLAN_TIMING") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    void mark(const char *phase) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[figaro plan] %-28s %9.3f s\n", phase, std::chrono::duration<double>(now - t).count());
+        t = now;
+    }
+};
+
 figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rels,
                     const figaro_plan_options *opts, hipStream_t stream) {
+    PhaseTimer timer;
     Builder B;
     B.p = p;
     B.r = r;
@@ -368,6 +438,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     }
     if (!keys_on_host && hipStreamSynchronize(stream) != hipSuccess)
         return set_error(p, FIGARO_EHIP, "hipStreamSynchronize failed");
+    timer.mark("keys to the host");
     // ---- dictionary-encode every attribute
     B.attr_bits.assign(B.attr_list.size(), 1);
     B.ids.resize(r);
@@ -381,18 +452,41 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             const int64_t *col = B.keys[i].data() + (size_t)kp * p->rel[i].m_in;
             vals.insert(vals.end(), col, col + p->rel[i].m_in);
         }
-        std::sort(vals.begin(), vals.end());
-        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        // dense ids in increasing key order: a presence table over the key
+        // range when it is small, else sort and binary search
+        int64_t lo = 0, hi = -1;
+        if (!vals.empty()) {
+            const auto mm = std::minmax_element(vals.begin(), vals.end());
+            lo = *mm.first;
+            hi = *mm.second;
+        }
+        const bool table = !vals.empty() && (uint64_t)(hi - lo) < (uint64_t)(8 * vals.size() + (1 << 20));
+        std::vector<int32_t> rank;
+        size_t distinct;
+        if (table) {
+            rank.assign((size_t)(hi - lo) + 1, 0);
+            for (int64_t v : vals) rank[(size_t)(v - lo)] = 1;
+            int32_t next = 0;
+            for (auto &x : rank) x = x ? next++ : -1;
+            distinct = (size_t)next;
+        } else {
+            std::sort(vals.begin(), vals.end());
+            vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+            distinct = vals.size();
+        }
         int bits = 1;
-        while ((int64_t(1) << bits) < (int64_t)vals.size()) ++bits;
+        while ((int64_t(1) << bits) < (int64_t)distinct) ++bits;
         B.attr_bits[ai] = bits;
         for (int i = 0; i < r; ++i) {
             int kp = B.key_pos(i, a);
             if (kp < 0) continue;
             const int64_t *col = B.keys[i].data() + (size_t)kp * p->rel[i].m_in;
             int32_t *out = B.ids[i].data() + (size_t)kp * p->rel[i].m_in;
-            for (int64_t t = 0; t < p->rel[i].m_in; ++t)
-                out[t] = (int32_t)(std::lower_bound(vals.begin(), vals.end(), col[t]) - vals.begin());
+            if (table)
+                for (int64_t t = 0; t < p->rel[i].m_in; ++t) out[t] = rank[(size_t)(col[t] - lo)];
+            else
+                for (int64_t t = 0; t < p->rel[i].m_in; ++t)
+                    out[t] = (int32_t)(std::lower_bound(vals.begin(), vals.end(), col[t]) - vals.begin());
         }
     }
     for (int i = 0; i < r; ++i) {
@@ -401,6 +495,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             return set_error(p, FIGARO_EUNSUPPORTED, "composite key of relation " + std::to_string(i) +
                                                          " needs more than 127 bits");
     }
+    timer.mark("dictionary encoding");
     // ---- semi-join reduction (bottom-up, then top-down)
     B.alive.resize(r);
     for (int i = 0; i < r; ++i) B.alive[i].assign(p->rel[i].m_in, 1);
@@ -409,15 +504,26 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         // occurs among the alive rows of probe_side
         std::vector<int32_t> sh = B.shared(keep_side, probe_side);
         Packer pk = B.make_packer(sh);
+        const std::vector<u128> pk_probe = B.pack_all(probe_side, pk);
+        const std::vector<u128> pk_keep = B.pack_all(keep_side, pk);
+        if (pk.bits <= KeyIndex::kDirectBits) {
+            // presence table over the packed keys
+            std::vector<char> present((size_t)1 << pk.bits, 0);
+            for (int64_t t = 0; t < p->rel[probe_side].m_in; ++t)
+                if (B.alive[probe_side][t]) present[(size_t)pk_probe[t]] = 1;
+            for (int64_t t = 0; t < p->rel[keep_side].m_in; ++t)
+                if (B.alive[keep_side][t] && !present[(size_t)pk_keep[t]]) B.alive[keep_side][t] = 0;
+            return;
+        }
         std::vector<u128> set;
         set.reserve(p->rel[probe_side].m_in);
         for (int64_t t = 0; t < p->rel[probe_side].m_in; ++t)
-            if (B.alive[probe_side][t]) set.push_back(B.pack(probe_side, t, pk));
-        std::sort(set.begin(), set.end());
+            if (B.alive[probe_side][t]) set.push_back(pk_probe[t]);
+        radix_sort_u128(set, pk.bits);
         set.erase(std::unique(set.begin(), set.end()), set.end());
+        const KeyIndex index(set, pk.bits);
         for (int64_t t = 0; t < p->rel[keep_side].m_in; ++t)
-            if (B.alive[keep_side][t] && !std::binary_search(set.begin(), set.end(), B.pack(keep_side, t, pk)))
-                B.alive[keep_side][t] = 0;
+            if (B.alive[keep_side][t] && index.find(pk_keep[t]) < 0) B.alive[keep_side][t] = 0;
     };
     for (int v : p->post)
         if (p->rel[v].parent >= 0) semijoin(p->rel[v].parent, v);
@@ -429,6 +535,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         p->rel[i].m = m;
         if (m == 0) return set_error(p, FIGARO_EEMPTY_JOIN, "the join is empty");
     }
+    timer.mark("semi-join reduction");
     // ---- sort, segment, parent groups
     std::vector<Packer> xp_pack(r), full_pack(r);
     std::vector<std::vector<u128>> pgroup_keys(r);
@@ -447,9 +554,25 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         const int rest_bits = full_pack[i].bits - xp_pack[i].bits;
         std::vector<std::pair<u128, int64_t>> kv;
         kv.reserve(R.m);
-        for (int64_t t = 0; t < R.m_in; ++t)
-            if (B.alive[i][t]) kv.emplace_back(B.pack(i, t, full_pack[i]), t);
-        std::sort(kv.begin(), kv.end());
+        {
+            const std::vector<u128> packed = B.pack_all(i, full_pack[i]);
+            int row_bits = 1;
+            while ((int64_t(1) << row_bits) < R.m_in) ++row_bits;
+            if (full_pack[i].bits + row_bits <= 128) {
+                // (key, row) in one 128-bit word: one comparison per step
+                std::vector<u128> w;
+                w.reserve(R.m);
+                for (int64_t t = 0; t < R.m_in; ++t)
+                    if (B.alive[i][t]) w.push_back((packed[t] << row_bits) | (u128)t);
+                radix_sort_u128(w, full_pack[i].bits + row_bits);
+                const u128 row_mask = ((u128)1 << row_bits) - 1;
+                for (u128 x : w) kv.emplace_back(x >> row_bits, (int64_t)(x & row_mask));
+            } else {
+                for (int64_t t = 0; t < R.m_in; ++t)
+                    if (B.alive[i][t]) kv.emplace_back(packed[t], t);
+                std::sort(kv.begin(), kv.end());
+            }
+        }
         R.perm.resize(R.m_in);
         for (int64_t q = 0; q < R.m; ++q) R.perm[q] = kv[q].second;
         int64_t q = R.m;
@@ -481,24 +604,24 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         if (!p->analyze_only && dev_upload(p, &R.d_perm, R.perm) != hipSuccess)
             return set_error(p, FIGARO_ENOMEM, "hipMalloc");
     }
+    timer.mark("sort and segments");
     // ---- child index of every key group
     std::vector<std::vector<std::vector<int32_t>>> cidx(r);
     for (int i = 0; i < r; ++i) {
         auto &R = p->rel[i];
         for (int c : R.children) {
             std::vector<int32_t> idx(R.G);
+            const KeyIndex index(pgroup_keys[c], xp_pack[c].bits);
+            const std::vector<u128> packed = B.pack_all(i, xp_pack[c]);
             for (int64_t g = 0; g < R.G; ++g) {
-                int64_t row = R.perm[R.seg_off[g]];
-                u128 k = B.pack(i, row, xp_pack[c]);
-                auto &keys = pgroup_keys[c];
-                auto it = std::lower_bound(keys.begin(), keys.end(), k);
-                if (it == keys.end() || *it != k)
-                    return set_error(p, FIGARO_EINVAL, "internal: unmatched key after reduction");
-                idx[g] = (int32_t)(it - keys.begin());
+                const int64_t q = index.find(packed[R.perm[R.seg_off[g]]]);
+                if (q < 0) return set_error(p, FIGARO_EINVAL, "internal: unmatched key after reduction");
+                idx[g] = (int32_t)q;
             }
             cidx[i].push_back(idx);
         }
     }
+    timer.mark("child indices");
     // ---- count queries, Algorithm 2
     auto check = [&](u128 v) { return v < (u128)kExactLimit; };
     for (int v : p->post) {   // pass 1: bottom-up
@@ -561,6 +684,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         }
     }
     if (p->analyze_only) return FIGARO_OK;
+    timer.mark("count queries");
     // ---- subtree columns, scale factors, head/tail tasks
     std::vector<std::vector<int32_t>> subtree_cols(r);
     for (int v : p->post) {
@@ -672,6 +796,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             if (dev_upload(p, &R.d_inv_sqrt_c, isc) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         }
     }
+    timer.mark("tasks and uploads");
     // ---- stack rows (fused R's of every launch, then the root rows) and R0 rows
     int64_t srow = 0, r0row = 0;
     for (int v : p->post) {
