@@ -118,17 +118,21 @@ struct Reflector {
 };
 
 __device__ __forceinline__ Reflector reflector(double p, double x2) {
-    const bool act = x2 > 0.0;
+    // act = 1 for x2 > 0, else 0; every quantity it multiplies is finite, so
+    // multiplying by it replaces the selects
+    const double act = (x2 > 0.0) ? 1.0 : 0.0;
     const double nrm = sqrt(fma(p, p, x2));
     const double beta = (p >= 0.0) ? -nrm : nrm;
-    const double den = act ? (p - beta) : 1.0;    // p - beta, |p - beta| >= nrm
-    const double bden = act ? beta : 1.0;
+    // (exact: one of the two terms of each sum is zero)
+    const double off = 1.0 - act;
+    const double den = fma(act, p - beta, off);      // p - beta (|p - beta| >= nrm), or 1
+    const double bden = fma(act, beta, off);         // beta, or 1
     const double inv_b = recip(bden);
     Reflector h;
     h.scale = recip(den);
-    h.tau = act ? -den * inv_b : 0.0;               // (beta - p) / beta
-    h.ts = act ? -inv_b : 0.0;                      // tau * scale
-    h.rjj = act ? beta : p;
+    h.tau = -act * den * inv_b;                      // (beta - p) / beta, or 0
+    h.ts = -act * inv_b;                             // tau * scale, or 0
+    h.rjj = fma(act, beta, off * p);                 // beta, or p
     return h;
 }
 
