@@ -306,10 +306,15 @@ class Plan:
 
     # -- data movement ------------------------------------------------------
     def to_plan_order(self, i: int, values, stream=None):
-        """(n_i, m_i) caller-order device tensor -> (n_i, kept rows) plan order."""
+        """(n_i, m_i) caller-order device tensor -> (n_i, kept rows) plan order.
+        The rows of the result are padded to a multiple of 16 doubles, so every
+        column starts 128-byte aligned (the head/tail kernels then stage full
+        tiles with 16-byte copies)."""
         import torch
         assert values.dtype == torch.float64 and values.is_cuda and values.stride(1) == 1
-        out = torch.empty((values.shape[0], self.rows(i)), dtype=torch.float64, device=values.device)
+        rows = self.rows(i)
+        ld = max((rows + 15) // 16 * 16, 16)
+        out = torch.empty((values.shape[0], ld), dtype=torch.float64, device=values.device)[:, :rows]
         _check(lib().figaro_permute_values(self._handle, i, ctypes.c_void_p(values.data_ptr()),
                                            values.stride(0), ctypes.c_void_p(out.data_ptr()),
                                            max(out.stride(0), 1), _stream_handle(stream)), self._handle)

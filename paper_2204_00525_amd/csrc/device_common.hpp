@@ -10,6 +10,10 @@ namespace {
 
 constexpr int kWavesPerBlock = 4;
 
+// s_waitcnt operand for "all vector memory operations done" (vmcnt 0,
+// expcnt and lgkmcnt at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
+
 // Butterfly all-reduce: partners add the same two operands (in either order,
 // which is exact), so every lane ends with the same bits; read lane 0 into
 // scalar registers to make that uniformity visible to the compiler.
@@ -25,6 +29,12 @@ __device__ __forceinline__ double lane_value(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t v, int src) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint64_t)v, src);
+    const int hi = __builtin_amdgcn_readlane((int)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // Move a double across lanes with a DPP control (two 32-bit halves); lanes
 // that a row mask disables keep `old`.
 template <int CTRL, int ROW_MASK = 0xF, int BANK_MASK = 0xF, bool BOUND_CTRL = true>
@@ -35,6 +45,14 @@ __device__ __forceinline__ double dpp(double v, double old) {
                                                BOUND_CTRL);
     return __hiloint2double(hi, lo);
 }
+
+// Whole-wave shifts by one lane with DPP (wave_shr:1 / wave_shl:1): lane l
+// receives lane l-1 (resp. l+1); lane 0 (resp. 63) keeps its own value.
+// Unlike a shuffle these stay in the vector ALU and never touch the LDS
+// pipe.
+__device__ __forceinline__ int wave_shr1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ int wave_shl1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ double wave_shr1(double v) { return dpp<0x138, 0xF, 0xF, false>(v, v); }
 
 // Sum over the 64 lanes with DPP moves: quad butterflies, half-row and row
 // mirrors give every lane its 16-lane row sum; two row broadcasts then fold
@@ -85,7 +103,7 @@ __device__ __forceinline__ void segmented_carry(double (&acc)[NB], uint64_t mask
         v = fma(dpp<0x118>(v, 0.0), m8, v);   // row_shr:8
         v = fma(dpp<0x142, 0xA, 0xF, false>(v, 0.0), m15, v);
         v = fma(dpp<0x143, 0xC, 0xF, false>(v, 0.0), m31, v);
-        acc[c] = __shfl_up(v, 1, 64) * m0;
+        acc[c] = wave_shr1(v) * m0;
     }
 }
 

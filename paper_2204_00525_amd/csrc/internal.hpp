@@ -36,6 +36,26 @@ constexpr int kChunkCols = 32;
 // heads.  The first item of a piece has no tail.  The kernel writes the sum
 // of every piece to `pieces_out` and either folds the tail rows into a
 // per-wave Householder R (mode FUSE) or writes them to an R0 buffer.
+// The joined heads of a relation read in place: process_and_join_children
+// (Algorithm 3) fused into the first level of project_away_join_attributes.
+// Column c of item (key group) g is
+//   own[idx[c]][g] * own_mult[g]                         if src[c] < 0,
+//   sigma_j[idx[c]][cidx_j[g]] * mult_j[g]               if src[c] = j,
+// the same products the separate join kernel would store.
+constexpr int kFuseMaxChildren = 4;
+struct JoinSrc {
+    const double *own;
+    int64_t ld_own;
+    const double *own_mult;
+    int32_t nchildren;
+    const double *sigma[kFuseMaxChildren];
+    int64_t ld_sigma[kFuseMaxChildren];
+    const int32_t *cidx[kFuseMaxChildren];
+    const double *mult[kFuseMaxChildren];
+    int8_t src[kMaxCols];
+    uint8_t idx[kMaxCols];
+};
+
 struct HelmertArgs {
     const double *in;
     int64_t ld_in;
@@ -47,6 +67,7 @@ struct HelmertArgs {
     const double *alpha;         // weighted mode: per-item tail coefficient of s
     const double *beta;          // weighted mode: per-item tail coefficient of P
     const int64_t *chunk_start;  // [nchunks+1]
+    const int32_t *chunk_piece0; // [nchunks+1] first piece id of every chunk
     int64_t nchunks;
     double *pieces_out;          // [ncols][ld_pieces] (may be null: no piece output)
     int64_t ld_pieces;
@@ -65,6 +86,11 @@ struct HelmertArgs {
     int32_t *block_of_row;
     int32_t block_id;
     int32_t waves;
+    // items read through a join view (first project-away level), columns
+    // join_col0 .. join_col0 + ncols - 1 of the joined heads
+    int32_t join;
+    int32_t join_col0;
+    JoinSrc js;
 };
 
 // Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
@@ -107,6 +133,8 @@ struct HelmertBwdArgs {
     int64_t ld_gout;
     int32_t gout_rowmajor;       // 1: item t, column c at gout[t * ld_gout + c]
     int32_t waves;
+    int32_t join;                // items read through js (see HelmertArgs)
+    JoinSrc js;
 };
 
 constexpr int kMaxChildren = 16;
@@ -232,7 +260,8 @@ struct Level {
     int32_t *d_pid = nullptr;
     int64_t *d_piece_start = nullptr;
     int64_t *d_chunk_start = nullptr;
-    double *d_phi_piece = nullptr;
+    int32_t *d_chunk_piece0 = nullptr;   // [nchunks+1] first piece of every chunk
+    double *d_phi_piece = nullptr;       // [npieces+1] (one entry of padding)
     double *d_alpha = nullptr, *d_beta = nullptr;
     double *d_pieces = nullptr;   // [ncols][npieces]
     double *d_gpieces = nullptr;  // gradient of the piece sums, [ncols][npieces]
@@ -282,7 +311,9 @@ struct RelPlan {
     std::vector<int32_t *> d_colpos;
     int8_t col_src[kMaxCols] = {};   // per subtree column: -1 own, else child index
     int8_t col_idx[kMaxCols] = {};   // per subtree column: column within its source
-    double *d_s = nullptr;           // [nsub][G]
+    bool fuse_join = false;          // joined heads read in place by the first project-away level
+    double *d_s = nullptr;           // [nsub][ld_s]
+    int64_t ld_s = 0;                // G rounded up to 16 (aligned columns)
     double *d_gs = nullptr;          // gradient of s, [nsub][G]
     std::vector<int64_t *> d_inv_off;   // per child: [P_child+1]
     std::vector<int32_t *> d_inv_idx;   // per child: [G]

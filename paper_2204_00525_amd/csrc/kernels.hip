@@ -281,6 +281,14 @@ __device__ __forceinline__ void store_r(const HelmertArgs &a, const double *rw, 
             a.stack[(int64_t)(64 * h + __builtin_ctzll(m)) * a.ld_stack + row] = 0.0;
 }
 
+// Whether the fused kernel of this shape stages its next tile in LDS: the
+// staging areas and R slices of the OCC workgroups a CU is meant to hold
+// must fit its 160 KiB of LDS.
+template <int NB, int RPL, bool ROT, int OCC>
+constexpr bool stage_fits() {
+    return OCC * kWavesPerBlock * 8 * (Stage<NB, RPL>::doubles + r_slice_doubles<NB, ROT>()) <= 160 * 1024;
+}
+
 // MODE 0: items count 1 each (tail coefficients from the position in the
 // piece); MODE 1: explicit per-item coefficients.  FUSE: fold the tails into
 // the running R of the wave, merge the waves of the workgroup and write one R
@@ -291,11 +299,21 @@ __device__ __forceinline__ void store_r(const HelmertArgs &a, const double *rw, 
 // barrier once its data chunks are done and then folds the other slices in
 // as extra tiles through the same QR call site.  Every wave executes exactly
 // one barrier and all branches around it are uniform within a wave.
+//
+// Staging (FUSE, where it fits): the asynchronous copies of the next chunk
+// are issued after the current chunk has been read from the staging area and
+// before its tails and QR are computed; they land while the QR runs.
 template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
+    // the compact QR's column loop reads R through loop-carried LDS addresses
+    // the compiler cannot tell apart from the staging area, so it would wait
+    // for the copies at its first column: no staging there
+    constexpr bool STAGE = FUSE && !ROT && stage_fits<NB, RPL, ROT, OCC>();
+    using S = Stage<NB, RPL>;
     __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB, ROT>() : 1];
+    __shared__ double stage_lds[STAGE ? kWavesPerBlock * S::doubles : 1];
     const int lane = threadIdx.x & 63;
-    const int wib = threadIdx.x >> 6;
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int wave = blockIdx.x * kWavesPerBlock + wib;
     const bool active = wave < a.waves;
     if (!FUSE && !active) return;
@@ -305,7 +323,48 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     if constexpr (FUSE) r_zero<NB, ROT>(rw, lane);
     const int64_t n_data = c_end - c_begin;
     const int64_t n_iter = n_data + ((FUSE && wib == 0) ? merge_tiles<NB, RPL>() : 0);
+    TailSrc src = tail_src(a);
+    src.pieces_out = a.pieces_out;
+    src.ld_pieces = a.ld_pieces;
 
+    // chunk boundaries (and first pieces) of chunks wbase .. wbase + 63, one
+    // per lane, read out with readlane: no wait on a global load between
+    // tiles except when the window moves on
+    int64_t wbase = c_begin, w_cs = 0;
+    int32_t w_p0 = 0;
+    auto window = [&](int64_t first) {
+        wbase = first;
+        const int64_t i = (first + lane < a.nchunks) ? first + lane : a.nchunks;
+        w_cs = a.chunk_start[i];
+        w_p0 = a.chunk_piece0[i];
+    };
+    auto bounds = [&](int64_t ch, int64_t &cs, int64_t &ce) {
+        if (ch + 2 - wbase > 63) window(ch);
+        const int i = (int)(ch - wbase);
+        cs = readlane64(w_cs, i);
+        ce = readlane64(w_cs, i + 1);
+    };
+    window(c_begin);
+
+    // staging: chunk c_begin + it + 1 is copied while chunk c_begin + it is
+    // worked on (full chunks with 16-byte aligned columns only).  The first
+    // chunk is read directly: a copy issued before the loop makes the
+    // compiler wait for it before every LDS read of the loop.
+    double *st = stage_lds + (STAGE ? wib * S::doubles : 0);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(a.in) & 15) == 0) && ((a.ld_in & 1) == 0);
+    bool staged = false;
+    int32_t staged_p0 = 0;
+    auto issue = [&](int64_t ch) {
+        int64_t cs, ce;
+        bounds(ch, cs, ce);
+        staged = aligned && ce - cs == S::T && (cs & 1) == 0;
+        if (staged) {
+            const int i = (int)(ch - wbase);
+            staged_p0 = MODE == 0 ? (__builtin_amdgcn_readlane(w_p0, i) & ~1) : 0;
+            const int32_t p1 = MODE == 0 ? __builtin_amdgcn_readlane(w_p0, i + 1) : 0;
+            stage_issue<NB, RPL, MODE>(src, cs, staged_p0, p1, st, lane);
+        }
+    };
     for (int64_t it = 0; it < n_iter; ++it) {
         double x[RPL][NB];
         if (FUSE && it >= n_data) {
@@ -313,12 +372,27 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
             merge_load<NB, RPL, ROT>(x, lane, (int)(it - n_data) * 64 * RPL, lds);
         } else {
             const int64_t ch = c_begin + it;
-            const int64_t cs = a.chunk_start[ch], ce = a.chunk_start[ch + 1];
+            int64_t cs, ce;
+            bounds(ch, cs, ce);
             TileItems<RPL> ti;
-            TailSrc src = tail_src(a);
-            src.pieces_out = a.pieces_out;
-            src.ld_pieces = a.ld_pieces;
-            tile_tails<NB, RPL, MODE, true>(src, cs, ce, lane, x, ti);
+            TileCoef<RPL> cf;
+            if (STAGE && staged) {
+                // the copies have landed; read them, and finish reading
+                // before the area is refilled
+                __builtin_amdgcn_s_waitcnt(kWaitVm0);
+                stage_read<NB, RPL, MODE>(src, cs, staged_p0, st, lane, x, ti, cf);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+            } else {
+                tile_load<NB, RPL, MODE>(src, cs, ce, lane, x, ti, cf);
+                // nothing of this chunk may stay in flight past the next
+                // chunk's copies (the compiler would then wait for those too)
+                if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(kWaitVm0);
+            }
+            if constexpr (STAGE) {
+                staged = false;
+                if (it + 1 < n_data) issue(ch + 1);
+            }
+            tile_finish<NB, RPL, MODE, true>(src, cs, lane, x, ti, cf);
             if constexpr (!FUSE) {
                 const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll

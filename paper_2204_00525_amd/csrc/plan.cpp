@@ -218,6 +218,7 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
         L.nchunks = (int64_t)cs.size() - 1;
         // pieces: chunk x group intersections
         std::vector<int32_t> pid(nitems);
+        std::vector<int32_t> cpiece(L.nchunks + 1);
         std::vector<int64_t> pstart;
         std::vector<int64_t> pgroup;
         std::vector<int64_t> pcount;
@@ -225,6 +226,7 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
         for (int64_t c = 0; c < L.nchunks; ++c) {
             int64_t a = cs[c], b = cs[c + 1];
             int64_t t = a;
+            cpiece[c] = (int32_t)pstart.size();
             while (t < b) {
                 while (goff[g + 1] <= t) ++g;
                 int64_t e = std::min(b, goff[g + 1]);
@@ -241,15 +243,17 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
             }
         }
         L.npieces = (int64_t)pstart.size();
-        if (L.npieces >= (int64_t(1) << 31))
+        if (L.npieces >= (int64_t(1) << 31) - 2)
             return set_error(p, FIGARO_EUNSUPPORTED, "too many pieces in one head/tail level");
+        cpiece[L.nchunks] = (int32_t)L.npieces;
         pstart.push_back(nitems);
         hipError_t e;
         if ((e = dev_upload(p, &L.d_pid, pid)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         if ((e = dev_upload(p, &L.d_piece_start, pstart)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         if ((e = dev_upload(p, &L.d_chunk_start, cs)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        if ((e = dev_upload(p, &L.d_chunk_piece0, cpiece)) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         if (unit) {
-            std::vector<double> pp(L.npieces);
+            std::vector<double> pp(L.npieces + 1, 0.0);   // one entry of padding for 16-byte copies
             for (int64_t q = 0; q < L.npieces; ++q) pp[q] = phi[pgroup[q]];
             if (dev_upload(p, &L.d_phi_piece, pp) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
         } else {
@@ -756,7 +760,8 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             }
             if (R.children.size() > (size_t)kMaxChildren)
                 return set_error(p, FIGARO_EUNSUPPORTED, "more than 16 children of one relation");
-            if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess ||
+            R.ld_s = (R.G + 15) / 16 * 16;
+            if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.ld_s) != hipSuccess ||
                 dev_alloc(p, (void **)&R.d_gs, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess)
                 return set_error(p, FIGARO_ENOMEM, "hipMalloc");
             // inverse of the child index: parent key groups grouped by child group

@@ -87,6 +87,7 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
         a.alpha = L.d_alpha;
         a.beta = L.d_beta;
         a.chunk_start = L.d_chunk_start;
+        a.chunk_piece0 = L.d_chunk_piece0;
         a.nchunks = L.nchunks;
         a.pieces_out = L.d_pieces;
         a.ld_pieces = L.npieces;
@@ -166,7 +167,7 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
             j.groups = Rl.G;
             j.nsub = Rl.nsub;
             j.s = Rl.d_s;
-            j.ld_s = Rl.G;
+            j.ld_s = Rl.ld_s;
             j.own = B.own[v];
             j.ld_own = B.ld_own[v];
             j.own_cols = Rl.ncols;
@@ -191,7 +192,7 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
                 FIGARO_TRY(launch_join(j, s));
             }
             items = Rl.d_s;
-            ld_items = Rl.G;
+            ld_items = Rl.ld_s;
         }
         if (Rl.parent >= 0) {
             // project_away_join_attributes (only non-leaves with P < G have tails)
@@ -319,7 +320,7 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
         const bool leaf = Rl.children.empty();
         // items of v after the join (s), and where their gradient lives
         const double *items = leaf ? B.own[v] : Rl.d_s;
-        const int64_t ld_items = leaf ? B.ld_own[v] : Rl.G;
+        const int64_t ld_items = leaf ? B.ld_own[v] : Rl.ld_s;
         const Target gs = leaf ? own_grad_target(p, v, dvalues, ld_dv) : Target{Rl.d_gs, Rl.nsub, true};
         if (Rl.parent < 0) {
             RootBwdArgs ra{};

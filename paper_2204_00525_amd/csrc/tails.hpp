@@ -58,18 +58,20 @@ struct TileItems {
     double al[RPL], be[RPL];
 };
 
+// Per-item inputs of the tail coefficients: MODE 0 the position j of the
+// item in its piece and the piece's scale phi; MODE 1 alpha and beta.
+template <int RPL>
+struct TileCoef {
+    double c0[RPL], c1[RPL];
+};
+
 // Loads the tile's columns into x (zero for invalid items and columns >=
-// ncols) and replaces them by the tail rows (zero for the first item of
-// every piece).  With PIECES, the sum of every piece is written to
-// pieces_out[c * ld_pieces + piece id] (if pieces_out is not null).
-//
-// Running sums are reset at piece starts by multiplying with a 0/1 factor
-// rather than by selects; a non-finite value therefore spreads into the
-// following pieces of the tile, which only matters for inputs that make R
-// non-finite anyway.
-template <int NB, int RPL, int MODE, bool PIECES>
-__device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t ce, int lane,
-                                           double (&x)[RPL][NB], TileItems<RPL> &ti) {
+// ncols), the piece ids and the coefficient inputs.  Every lane loads its
+// coefficients (clamped indices for items past the end or the first item of
+// a piece), so no load sits under a divergent branch.
+template <int NB, int RPL, int MODE>
+__device__ __forceinline__ void tile_load(const TailSrc &a, int64_t cs, int64_t ce, int lane,
+                                          double (&x)[RPL][NB], TileItems<RPL> &ti, TileCoef<RPL> &cf) {
     const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
@@ -83,10 +85,35 @@ __device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t
 #pragma unroll
         for (int k = 0; k < RPL; ++k) x[k][c] = (live && ti.valid[k]) ? col[base + k] : 0.0;
     }
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        if constexpr (MODE == 0) {
+            const int32_t p = ti.valid[k] ? ti.pid[k] : a.pid[cs];
+            cf.c0[k] = (double)(base + k - a.piece_start[p]);
+            cf.c1[k] = a.phi_piece[p];
+        } else {
+            const int64_t tc = ti.valid[k] ? base + k : cs;
+            cf.c0[k] = a.alpha[tc];
+            cf.c1[k] = a.beta[tc];
+        }
+    }
+}
+
+// Replaces the loaded columns by the tail rows (zero for the first item of
+// every piece).  With PIECES, the sum of every piece is written to
+// pieces_out[c * ld_pieces + piece id] (if pieces_out is not null).
+//
+// Running sums are reset at piece starts by multiplying with a 0/1 factor
+// rather than by selects; a non-finite value therefore spreads into the
+// following pieces of the tile, which only matters for inputs that make R
+// non-finite anyway.
+template <int NB, int RPL, int MODE, bool PIECES>
+__device__ __forceinline__ void tile_finish(const TailSrc &a, int64_t cs, int lane, double (&x)[RPL][NB],
+                                            TileItems<RPL> &ti, const TileCoef<RPL> &cf) {
     // piece starts: the chunk's first item, and every change of piece id
-    // (shuffle unconditionally: under a divergent mask it would read an
-    // inactive lane)
-    const int32_t prev_last = __shfl_up(ti.pid[RPL - 1], 1, 64);
+    // (the lane shifts run unconditionally: under a divergent mask they
+    // would read an inactive lane)
+    const int32_t prev_last = wave_shr1(ti.pid[RPL - 1]);
     double keep[RPL];
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
@@ -108,28 +135,22 @@ __device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t
         acc[c] = sum;
     }
     segmented_carry<NB>(acc, __ballot(lane_flag), lane);
-    const int nf0 = __shfl_down((int)ti.first[0], 1, 64);
+    const int nf0 = wave_shl1((int)ti.first[0]);
     const bool next_first0 = (lane == 63) || (nf0 != 0);
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-        const int64_t t = base + k;
         const bool use = ti.valid[k] && !ti.first[k];
         double al = 0.0, be = 0.0;
         if constexpr (MODE == 0) {
             if (use) {
-                const double j = (double)(t - a.piece_start[ti.pid[k]]);
+                const double j = cf.c0[k];
                 const double q = 1.0 / sqrt(j * (j + 1.0));
-                const double phi = a.phi_piece[ti.pid[k]];
-                al = phi * j * q;
-                be = phi * q;
+                al = cf.c1[k] * j * q;
+                be = cf.c1[k] * q;
             }
         } else {
-            // branch-free: every lane loads (a clamped index for items past
-            // the end), the piece start selects zero
-            const int64_t tc = ti.valid[k] ? t : cs;
-            const double a0 = a.alpha[tc], b0 = a.beta[tc];
-            al = use ? a0 : 0.0;
-            be = use ? b0 : 0.0;
+            al = use ? cf.c0[k] : 0.0;
+            be = use ? cf.c1[k] : 0.0;
         }
         ti.al[k] = al;
         ti.be[k] = be;
@@ -147,6 +168,112 @@ __device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t
                 for (int c = 0; c < NB; ++c)
                     if (c < a.ncols) a.pieces_out[(int64_t)c * a.ld_pieces + ti.pid[k]] = acc[c];
             }
+        }
+    }
+}
+
+template <int NB, int RPL, int MODE, bool PIECES>
+__device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t ce, int lane,
+                                           double (&x)[RPL][NB], TileItems<RPL> &ti) {
+    TileCoef<RPL> cf;
+    tile_load<NB, RPL, MODE>(a, cs, ce, lane, x, ti, cf);
+    tile_finish<NB, RPL, MODE, PIECES>(a, cs, lane, x, ti, cf);
+}
+
+// ---------------------------------------------------------------------------
+// Staging of the next tile in LDS.  A wave that processes consecutive chunks
+// copies the next full chunk (64*RPL items) from global memory into its own
+// LDS area with asynchronous global-to-LDS loads (16 bytes per lane, no
+// registers held while they fly) and works on the current tile meanwhile.
+// Layout of a wave's area, T = 64*RPL: the NB columns of the tile ([NB][T]
+// doubles), the two coefficient inputs ([T] doubles each: alpha and beta, or
+// for MODE 0 the window of phi and of the piece starts of the chunk's
+// pieces), the piece ids ([T] int32).
+template <int NB, int RPL>
+struct Stage {
+    static constexpr int T = 64 * RPL;
+    static constexpr int W = T + 2;             // window entries (even start)
+    static constexpr int C0 = NB * T;
+    static constexpr int C1 = C0 + W;
+    static constexpr int PID = C1 + W;          // in doubles; T int32 follow
+    static constexpr int doubles = PID + T / 2;
+};
+
+__device__ __forceinline__ void lds_copy16(const void *src, void *dst) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+}
+
+__device__ __forceinline__ void lds_copy4(const void *src, void *dst) {
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+}
+
+// n (<= N) 8-byte entries from src to dst (both 16-byte aligned); lane l
+// copies entries 128 q + 2 l and 128 q + 2 l + 1.  Reads entry n when n is
+// odd (the caller guarantees it exists).
+template <int N>
+__device__ __forceinline__ void stage_span(const void *src, void *dst, int n, int lane) {
+    const char *s = (const char *)src;
+    char *d = (char *)dst;
+#pragma unroll
+    for (int q = 0; q < (N + 127) / 128; ++q) {
+        const int e = 128 * q + 2 * lane;
+        if (e < n) lds_copy16(s + 8 * (int64_t)e, d + 8 * 128 * q);
+    }
+}
+
+// Issue the copies of chunk [cs, cs + T) (a full chunk; the columns start
+// 16-byte aligned).  MODE 0 copies the window of the chunk's pieces from the
+// even id p0 to p1 - 1.
+template <int NB, int RPL, int MODE>
+__device__ __forceinline__ void stage_issue(const TailSrc &a, int64_t cs, int32_t p0, int32_t p1, double *st,
+                                            int lane) {
+    using S = Stage<NB, RPL>;
+    constexpr int T = S::T;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        if (c < a.ncols) stage_span<T>(a.in + (int64_t)c * a.ld_in + cs, st + c * T, T, lane);
+    if constexpr (MODE == 0) {
+        stage_span<S::W>(a.phi_piece + p0, st + S::C0, p1 - p0, lane);
+        stage_span<S::W>(a.piece_start + p0, st + S::C1, p1 - p0, lane);
+    } else {
+        stage_span<T>(a.alpha + cs, st + S::C0, T, lane);
+        stage_span<T>(a.beta + cs, st + S::C1, T, lane);
+    }
+    int32_t *pid = (int32_t *)(st + S::PID);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) lds_copy4(a.pid + cs + 64 * q + lane, pid + 64 * q);
+}
+
+// The staged chunk into registers (all items valid).
+template <int NB, int RPL, int MODE>
+__device__ __forceinline__ void stage_read(const TailSrc &a, int64_t cs, int32_t p0, const double *st, int lane,
+                                           double (&x)[RPL][NB], TileItems<RPL> &ti, TileCoef<RPL> &cf) {
+    using S = Stage<NB, RPL>;
+    constexpr int T = S::T;
+    const int r0 = lane * RPL;
+    const int32_t *pid = (const int32_t *)(st + S::PID);
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        ti.valid[k] = true;
+        ti.pid[k] = pid[r0 + k];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) x[k][c] = (c < a.ncols) ? st[c * T + r0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        if constexpr (MODE == 0) {
+            const int w = ti.pid[k] - p0;
+            const int64_t *ps = (const int64_t *)(st + S::C1);
+            cf.c0[k] = (double)(cs + r0 + k - ps[w]);
+            cf.c1[k] = st[S::C0 + w];
+        } else {
+            cf.c0[k] = st[S::C0 + r0 + k];
+            cf.c1[k] = st[S::C1 + r0 + k];
         }
     }
 }

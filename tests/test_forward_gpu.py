@@ -95,6 +95,32 @@ def test_forward_small_tiles_split_groups(F, oracle_lib, name, tile):
     assert _relf(R, ref) <= TOL
 
 
+STAGED = {
+    # unit-count first level (heads_and_tails), 16 columns per relation
+    "two_rel_zipf": lambda: synth.two_relation(10, 20000, 20000, 16, 16, 200, dist="zipf"),
+    # weighted first level of project_away_join_attributes (middle of a chain)
+    "chain3_mid": lambda: synth.random_chain(21, 3, 6000, 5, 600),
+    # weighted first level over the fact table under a dimension root
+    "star_dim_root_9": lambda: synth.random_star(22, 4, 6000, 40, 3, root=1),
+}
+
+
+@pytest.mark.parametrize("waves", [1, 3])
+@pytest.mark.parametrize("name", sorted(STAGED))
+def test_forward_staged_tiles(F, oracle_lib, name, waves):
+    """Few waves per task: every wave works through many full chunks and
+    copies each next chunk into LDS while it folds the current one (with one
+    wave it also moves its window of chunk boundaries); the last chunk of a
+    level is ragged and read directly.  R must not change."""
+    inst = STAGED[name]()
+    _say(f"[forward-staged] case={name} waves={waves}")
+    R, plan, _ = gpu_r(F, inst, waves_per_task=waves)
+    ref = oracle_lib.r_of_join(inst)
+    err = _relf(R, ref)
+    _say(f"[forward-staged] case={name} waves={waves} join_rows={plan.join_rows:.0f} rel_err={err:.3e}")
+    assert err <= TOL
+
+
 def test_forward_deterministic(F):
     inst = CASES["two_rel_zipf"]()
     import torch
