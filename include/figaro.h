@@ -105,6 +105,12 @@ typedef struct {
                                    then answers the info and count queries
                                    only, holds no device memory, and the
                                    compute calls return FIGARO_EINVAL */
+    int32_t separate_join;      /* 1: always store the joined heads of a
+                                   relation (process_and_join_children) before
+                                   projecting the join attributes away; 0
+                                   (default): a non-root relation with at most
+                                   four children has its first project-away
+                                   level read them in place instead */
 } figaro_plan_options;
 
 /* Count-query selectors for figaro_plan_counts(). */

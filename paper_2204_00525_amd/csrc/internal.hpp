@@ -39,9 +39,11 @@ constexpr int kChunkCols = 32;
 // The joined heads of a relation read in place: process_and_join_children
 // (Algorithm 3) fused into the first level of project_away_join_attributes.
 // Column c of item (key group) g is
-//   own[idx[c]][g] * own_mult[g]                         if src[c] < 0,
-//   sigma_j[idx[c]][cidx_j[g]] * mult_j[g]               if src[c] = j,
-// the same products the separate join kernel would store.
+//   own[idx[c] * ld_own + g] * own_mult[g]                       if src[c] < 0,
+//   sigma_j[cidx_j[g] * ld_sigma_j + idx[c]] * mult_j[g]         if src[c] = j,
+// the same products the separate join kernel would store.  The children's
+// sums are row-major here, so the columns of one child group share a cache
+// line.
 constexpr int kFuseMaxChildren = 4;
 struct JoinSrc {
     const double *own;
@@ -52,8 +54,10 @@ struct JoinSrc {
     int64_t ld_sigma[kFuseMaxChildren];
     const int32_t *cidx[kFuseMaxChildren];
     const double *mult[kFuseMaxChildren];
-    int8_t src[kMaxCols];
-    uint8_t idx[kMaxCols];
+    // per joined column: (source + 1) << 8 | column within the source, with
+    // source -1 for the own sums and j for child j (32-bit words, so the
+    // kernel reads them with scalar loads)
+    int32_t code[kMaxCols];
 };
 
 struct HelmertArgs {
@@ -133,8 +137,6 @@ struct HelmertBwdArgs {
     int64_t ld_gout;
     int32_t gout_rowmajor;       // 1: item t, column c at gout[t * ld_gout + c]
     int32_t waves;
-    int32_t join;                // items read through js (see HelmertArgs)
-    JoinSrc js;
 };
 
 constexpr int kMaxChildren = 16;
@@ -221,6 +223,7 @@ struct RootBwdArgs {
 hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s);
 hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s);
 hipError_t launch_join(const JoinArgs &a, hipStream_t s);
+hipError_t launch_rowmajor(const double *src, int64_t ld_src, int64_t rows, int32_t ncols, double *dst, hipStream_t s);
 hipError_t launch_root(const RootArgs &a, bool to_r0, hipStream_t s);
 hipError_t launch_permute(const double *src, int64_t ld_src, double *dst, int64_t ld_dst,
                           const int64_t *perm, int64_t rows, int32_t ncols, bool inverse,
@@ -309,6 +312,7 @@ struct RelPlan {
     std::vector<int32_t *> d_cidx;
     std::vector<double *> d_mult;
     std::vector<int32_t *> d_colpos;
+    std::vector<double *> d_sigma_rm;   // fused join: row-major copy of every child's sums [P_child][nsub_child]
     int8_t col_src[kMaxCols] = {};   // per subtree column: -1 own, else child index
     int8_t col_idx[kMaxCols] = {};   // per subtree column: column within its source
     bool fuse_join = false;          // joined heads read in place by the first project-away level
@@ -352,6 +356,7 @@ struct figaro_plan_s {
     int32_t tile_items = 0;
     int32_t waves_cap = 0;
     bool analyze_only = false;
+    bool separate_join = false;
     int32_t variant = 0;
     // stack for the post-processing TSQR
     int64_t stack_rows = 0;

@@ -290,7 +290,9 @@ constexpr bool stage_fits() {
 }
 
 // MODE 0: items count 1 each (tail coefficients from the position in the
-// piece); MODE 1: explicit per-item coefficients.  FUSE: fold the tails into
+// piece); MODE 1: explicit per-item coefficients.  JOIN: the items are the
+// joined heads, read in place through a.js (the first level of
+// project_away_join_attributes fused with process_and_join_children).  FUSE: fold the tails into
 // the running R of the wave, merge the waves of the workgroup and write one R
 // per workgroup; otherwise write the tail rows to the R0 buffer.
 //
@@ -303,15 +305,16 @@ constexpr bool stage_fits() {
 // Staging (FUSE, where it fits): the asynchronous copies of the next chunk
 // are issued after the current chunk has been read from the staging area and
 // before its tails and QR are computed; they land while the QR runs.
-template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT>
+template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT, bool JOIN>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
     // the compact QR's column loop reads R through loop-carried LDS addresses
     // the compiler cannot tell apart from the staging area, so it would wait
     // for the copies at its first column: no staging there
-    constexpr bool STAGE = FUSE && !ROT && stage_fits<NB, RPL, ROT, OCC>();
+    constexpr bool STAGE = FUSE && !ROT && !JOIN && stage_fits<NB, RPL, ROT, OCC>();
     using S = Stage<NB, RPL>;
     __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB, ROT>() : 1];
     __shared__ double stage_lds[STAGE ? kWavesPerBlock * S::doubles : 1];
+    __shared__ int32_t prefetch_sink[JOIN ? 64 : 1];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int wave = blockIdx.x * kWavesPerBlock + wib;
@@ -383,7 +386,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                 stage_read<NB, RPL, MODE>(src, cs, staged_p0, st, lane, x, ti, cf);
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             } else {
-                tile_load<NB, RPL, MODE>(src, cs, ce, lane, x, ti, cf);
+                tile_load<NB, RPL, MODE, JOIN>(src, cs, ce, lane, x, ti, cf, &a.js, a.join_col0);
+                if constexpr (JOIN && FUSE) {
+                    if (it + 1 < n_data) {
+                        int64_t ncs, nce;
+                        bounds(ch + 1, ncs, nce);
+                        join_prefetch<RPL>(a.js, ncs, nce, lane, prefetch_sink);
+                    }
+                }
                 // nothing of this chunk may stay in flight past the next
                 // chunk's copies (the compiler would then wait for those too)
                 if constexpr (STAGE) __builtin_amdgcn_s_waitcnt(kWaitVm0);
@@ -611,6 +621,13 @@ __global__ void k_join(JoinArgs a) {
 }
 
 // One thread per (root key group, column).
+// Column-major [ncols][ld_src] -> row-major [rows][ncols] (one thread per row).
+__global__ void k_rowmajor(const double *src, int64_t ld_src, int64_t rows, int32_t ncols, double *dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows) return;
+    for (int c = 0; c < ncols; ++c) dst[t * ncols + c] = src[(int64_t)c * ld_src + t];
+}
+
 __global__ void k_root(RootArgs a) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
@@ -672,12 +689,17 @@ hipError_t helmert_nb(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s)
     constexpr int RPL = Shape<NB, V>::RPL, OCC = Shape<NB, V>::OCC;
     constexpr bool ROT = Shape<NB, V>::ROT;
     dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock), block(64 * kWavesPerBlock);
-    if (unit) {
-        if (fuse) hipLaunchKernelGGL((k_helmert<NB, RPL, 0, true, OCC, ROT>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_helmert<NB, RPL, 0, false, OCC, ROT>), grid, block, 0, s, a);
+    if (a.join) {
+        // joined heads are key groups with counts: weighted tails only
+        if (unit) return hipErrorInvalidValue;
+        if (fuse) hipLaunchKernelGGL((k_helmert<NB, RPL, 1, true, OCC, ROT, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_helmert<NB, RPL, 1, false, OCC, ROT, true>), grid, block, 0, s, a);
+    } else if (unit) {
+        if (fuse) hipLaunchKernelGGL((k_helmert<NB, RPL, 0, true, OCC, ROT, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_helmert<NB, RPL, 0, false, OCC, ROT, false>), grid, block, 0, s, a);
     } else {
-        if (fuse) hipLaunchKernelGGL((k_helmert<NB, RPL, 1, true, OCC, ROT>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_helmert<NB, RPL, 1, false, OCC, ROT>), grid, block, 0, s, a);
+        if (fuse) hipLaunchKernelGGL((k_helmert<NB, RPL, 1, true, OCC, ROT, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_helmert<NB, RPL, 1, false, OCC, ROT, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
@@ -778,6 +800,14 @@ hipError_t launch_join(const JoinArgs &a, hipStream_t s) {
     if (a.groups <= 0 || a.nsub <= 0) return hipSuccess;
     const int bs = 256;
     hipLaunchKernelGGL(k_join, dim3((unsigned)((a.groups + bs - 1) / bs), (unsigned)a.nsub), dim3(bs), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowmajor(const double *src, int64_t ld_src, int64_t rows, int32_t ncols, double *dst, hipStream_t s) {
+    if (rows <= 0 || ncols <= 0) return hipSuccess;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_rowmajor, dim3((unsigned)((rows + bs - 1) / bs)), dim3(bs), 0, s, src, ld_src, rows, ncols,
+                       dst);
     return hipGetLastError();
 }
 

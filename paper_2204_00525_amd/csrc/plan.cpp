@@ -331,6 +331,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     const bool keys_on_host = opts && opts->keys_on_host;
     p->analyze_only = opts && opts->analyze_only;
     p->variant = opts ? opts->variant : 0;
+    p->separate_join = opts && opts->separate_join;
     if (p->variant < 0 || p->variant >= num_variants())
         return set_error(p, FIGARO_EINVAL, "variant out of range");
     if (p->tile_items < 0) return set_error(p, FIGARO_EINVAL, "tile_items must be >= 0");
@@ -760,6 +761,20 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             }
             if (R.children.size() > (size_t)kMaxChildren)
                 return set_error(p, FIGARO_EUNSUPPORTED, "more than 16 children of one relation");
+            // the forward pass reads the joined heads of a relation that
+            // projects its join attributes away in place (first head/tail
+            // level) when it has at most kFuseMaxChildren children; the
+            // backward pass, which reads them twice, stores them
+            R.fuse_join = R.parent >= 0 && R.P < R.G && R.children.size() <= (size_t)kFuseMaxChildren &&
+                          !p->separate_join;
+            if (R.fuse_join)
+                for (int ch : R.children) {
+                    double *rm;
+                    const auto &C = p->rel[ch];
+                    if (dev_alloc(p, (void **)&rm, sizeof(double) * (size_t)C.P * (size_t)C.nsub) != hipSuccess)
+                        return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+                    R.d_sigma_rm.push_back(rm);
+                }
             R.ld_s = (R.G + 15) / 16 * 16;
             if (dev_alloc(p, (void **)&R.d_s, sizeof(double) * (size_t)R.nsub * (size_t)R.ld_s) != hipSuccess ||
                 dev_alloc(p, (void **)&R.d_gs, sizeof(double) * (size_t)R.nsub * (size_t)R.G) != hipSuccess)

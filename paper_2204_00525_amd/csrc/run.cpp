@@ -69,16 +69,39 @@ figaro_status check_inputs(figaro_plan_s *p, const double *const *values, const 
     return FIGARO_OK;
 }
 
-// Run the levels of one head/tail task; returns the group sums.
+// The joined heads of relation v read in place (its first project-away
+// level fused with process_and_join_children).
+JoinSrc join_src(const figaro_plan_s *p, const RelPlan &Rl, int v, const Buffers &B) {
+    JoinSrc js{};
+    js.own = B.own[v];
+    js.ld_own = B.ld_own[v];
+    js.own_mult = Rl.d_own_mult;
+    js.nchildren = (int32_t)Rl.children.size();
+    for (size_t c = 0; c < Rl.children.size(); ++c) {
+        js.sigma[c] = Rl.d_sigma_rm[c];
+        js.ld_sigma[c] = p->rel[Rl.children[c]].nsub;
+        js.cidx[c] = Rl.d_cidx[c];
+        js.mult[c] = Rl.d_mult[c];
+    }
+    for (int c = 0; c < Rl.nsub; ++c) js.code[c] = ((int32_t)Rl.col_src[c] + 1) << 8 | (uint8_t)Rl.col_idx[c];
+    return js;
+}
+
+// Run the levels of one head/tail task; returns the group sums.  With js,
+// the first level reads its items through the join view (in is unused).
 figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_in, bool fuse, double *r0,
                        int64_t ld_r0, int32_t *block_of_row, hipStream_t s, const double **group_sums,
-                       int64_t *ld_groups) {
+                       int64_t *ld_groups, const JoinSrc *js = nullptr) {
     const double *cur = in;
     int64_t ld = ld_in;
     for (auto &L : T.levels) {
         HelmertArgs a{};
         a.in = cur;
         a.ld_in = ld;
+        if (js && &L == &T.levels[0]) {
+            a.join = 1;
+            a.js = *js;
+        }
         a.ncols = T.ncols;
         a.items = L.items;
         a.pid = L.d_pid;
@@ -122,7 +145,8 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
                 // columns outside the task
                 for (int c0 = 0; c0 < T.ncols; c0 += kChunkCols) {
                     HelmertArgs ac = a;
-                    ac.in = cur + (int64_t)c0 * ld;
+                    ac.in = a.join ? nullptr : cur + (int64_t)c0 * ld;
+                    ac.join_col0 = c0;
                     ac.ncols = std::min(kChunkCols, T.ncols - c0);
                     ac.pieces_out = L.d_pieces + (int64_t)c0 * L.npieces;
                     for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint8_t)T.cols[c0 + c];
@@ -142,7 +166,11 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
 figaro_status forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse, double *R,
                       double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, bool stop_before_tsqr = false,
                       Buffers *keep = nullptr) {
-    // produce-only mode (fuse false, r0 null): piece sums and joined heads only
+    // produce-only mode (fuse false, r0 null): piece sums and joined heads only.
+    // The joined heads are read in place (fused relations) except when the
+    // pass recomputes them for the backward pass (keep), which reads them
+    // again and wants them stored.
+    const bool join_in_place = keep == nullptr;
     Buffers B;
     B.own.assign(p->r, nullptr);
     B.ld_own.assign(p->r, 0);
@@ -161,7 +189,8 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
         }
         const double *items = B.own[v];
         int64_t ld_items = B.ld_own[v];
-        if (!Rl.children.empty()) {
+        const bool in_place = Rl.fuse_join && join_in_place;
+        if (!Rl.children.empty() && !in_place) {
             // process_and_join_children
             JoinArgs j{};
             j.groups = Rl.G;
@@ -197,8 +226,18 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
         if (Rl.parent >= 0) {
             // project_away_join_attributes (only non-leaves with P < G have tails)
             if (Rl.a4.active) {
+                JoinSrc js;
+                if (in_place) {
+                    // the children's sums, row-major
+                    for (size_t c = 0; c < Rl.children.size(); ++c) {
+                        const int ch = Rl.children[c];
+                        FIGARO_TRY(launch_rowmajor(B.sigma[ch], B.ld_sigma[ch], p->rel[ch].P, p->rel[ch].nsub,
+                                                   Rl.d_sigma_rm[c], s));
+                    }
+                    js = join_src(p, Rl, v, B);
+                }
                 figaro_status st = run_task(p, Rl.a4, items, ld_items, fuse, r0, ld_r0, block_of_row, s,
-                                            &B.sigma[v], &B.ld_sigma[v]);
+                                            &B.sigma[v], &B.ld_sigma[v], in_place ? &js : nullptr);
                 if (st != FIGARO_OK) return st;
             } else {
                 B.sigma[v] = items;

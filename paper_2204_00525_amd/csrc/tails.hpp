@@ -65,25 +65,90 @@ struct TileCoef {
     double c0[RPL], c1[RPL];
 };
 
+// Columns col0 .. col0 + NB - 1 of the joined heads of items
+// base .. base + RPL - 1 read in place (JoinSrc): own sums times own_mult,
+// or a child's sums at the child group of the item times that child's mult.
+// The source of a column is uniform over the wave; its base address, stride
+// and factor are picked with selects, so the loads of all columns are
+// branch-free and in flight together.  The products are rounded as such
+// (never contracted into a later addition), exactly as the stored joined
+// heads would be.
+template <int NB, int RPL>
+__device__ __forceinline__ void join_load(const JoinSrc &js, int col0, int ncols, int64_t base, const bool (&valid)[RPL],
+                                          int64_t tclamp, double (&x)[RPL][NB]) {
+    int64_t t[RPL];
+    double om[RPL];
+    int32_t ci[kFuseMaxChildren][RPL];
+    double mu[kFuseMaxChildren][RPL];
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+        t[k] = valid[k] ? base + k : tclamp;
+        om[k] = js.own_mult[t[k]];
+#pragma unroll
+        for (int j = 0; j < kFuseMaxChildren; ++j) {
+            const bool has = j < js.nchildren;
+            ci[j][k] = has ? js.cidx[j][t[k]] : 0;
+            mu[j][k] = has ? js.mult[j][t[k]] : 0.0;
+        }
+    }
+    // all loads first (nothing waits on them inside the column loop), then
+    // the products
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const bool live = c < ncols;
+        const int code = js.code[live ? col0 + c : col0];
+        const int src = (code >> 8) - 1, q = code & 0xff;
+        const bool own = src < 0;
+        const int sj = own ? 0 : src;
+        const double *colp = own ? js.own + (int64_t)q * js.ld_own : js.sigma[sj] + q;
+        const int64_t ld = own ? 1 : js.ld_sigma[sj];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            int32_t g = ci[0][k];
+#pragma unroll
+            for (int j = 1; j < kFuseMaxChildren; ++j) g = (sj == j) ? ci[j][k] : g;
+            x[k][c] = colp[own ? t[k] : (int64_t)g * ld];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const bool live = c < ncols;
+        const int src = (js.code[live ? col0 + c : col0] >> 8) - 1;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            double m = om[k];
+#pragma unroll
+            for (int j = 0; j < kFuseMaxChildren; ++j) m = (src == j) ? mu[j][k] : m;
+            x[k][c] = (live && valid[k]) ? __dmul_rn(x[k][c], m) : 0.0;
+        }
+    }
+}
+
 // Loads the tile's columns into x (zero for invalid items and columns >=
 // ncols), the piece ids and the coefficient inputs.  Every lane loads its
 // coefficients (clamped indices for items past the end or the first item of
-// a piece), so no load sits under a divergent branch.
-template <int NB, int RPL, int MODE>
+// a piece), so no load sits under a divergent branch.  JOIN: the columns are
+// those of the joined heads, read through js from column col0 on.
+template <int NB, int RPL, int MODE, bool JOIN = false>
 __device__ __forceinline__ void tile_load(const TailSrc &a, int64_t cs, int64_t ce, int lane,
-                                          double (&x)[RPL][NB], TileItems<RPL> &ti, TileCoef<RPL> &cf) {
+                                          double (&x)[RPL][NB], TileItems<RPL> &ti, TileCoef<RPL> &cf,
+                                          const JoinSrc *js = nullptr, int col0 = 0) {
     const int64_t base = cs + (int64_t)lane * RPL;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
         ti.valid[k] = base + k < ce;
         ti.pid[k] = ti.valid[k] ? a.pid[base + k] : -1;
     }
+    if constexpr (JOIN) {
+        join_load<NB, RPL>(*js, col0, a.ncols, base, ti.valid, cs, x);
+    } else {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        const bool live = c < a.ncols;
-        const double *col = a.in + (int64_t)(live ? c : 0) * a.ld_in;
+        for (int c = 0; c < NB; ++c) {
+            const bool live = c < a.ncols;
+            const double *col = a.in + (int64_t)(live ? c : 0) * a.ld_in;
 #pragma unroll
-        for (int k = 0; k < RPL; ++k) x[k][c] = (live && ti.valid[k]) ? col[base + k] : 0.0;
+            for (int k = 0; k < RPL; ++k) x[k][c] = (live && ti.valid[k]) ? col[base + k] : 0.0;
+        }
     }
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
@@ -172,13 +237,21 @@ __device__ __forceinline__ void tile_finish(const TailSrc &a, int64_t cs, int la
     }
 }
 
-template <int NB, int RPL, int MODE, bool PIECES>
+template <int NB, int RPL, int MODE, bool PIECES, bool JOIN = false>
 __device__ __forceinline__ void tile_tails(const TailSrc &a, int64_t cs, int64_t ce, int lane,
-                                           double (&x)[RPL][NB], TileItems<RPL> &ti) {
+                                           double (&x)[RPL][NB], TileItems<RPL> &ti,
+                                           const JoinSrc *js = nullptr, int col0 = 0) {
     TileCoef<RPL> cf;
-    tile_load<NB, RPL, MODE>(a, cs, ce, lane, x, ti, cf);
+    tile_load<NB, RPL, MODE, JOIN>(a, cs, ce, lane, x, ti, cf, js, col0);
     tile_finish<NB, RPL, MODE, PIECES>(a, cs, lane, x, ti, cf);
 }
+
+// Early fetch of the children's rows of the items cs .. ce - 1 (the next
+// chunk) into the caches: a 4-byte asynchronous copy of each row start into
+// a scratch LDS word that nobody reads.  The wave does not wait for these;
+// by the time it gathers the rows they are close.
+template <int RPL>
+__device__ __forceinline__ void join_prefetch(const JoinSrc &js, int64_t cs, int64_t ce, int lane, void *sink);
 
 // ---------------------------------------------------------------------------
 // Staging of the next tile in LDS.  A wave that processes consecutive chunks
@@ -207,6 +280,22 @@ __device__ __forceinline__ void lds_copy16(const void *src, void *dst) {
 __device__ __forceinline__ void lds_copy4(const void *src, void *dst) {
     __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
                                      (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+}
+
+template <int RPL>
+__device__ __forceinline__ void join_prefetch(const JoinSrc &js, int64_t cs, int64_t ce, int lane, void *sink) {
+    const int64_t base = cs + (int64_t)lane * RPL;
+#pragma unroll
+    for (int j = 0; j < kFuseMaxChildren; ++j) {
+        if (j < js.nchildren) {
+            int32_t g[RPL];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) g[k] = js.cidx[j][base + k < ce ? base + k : cs];
+#pragma unroll
+            for (int k = 0; k < RPL; ++k)
+                if (base + k < ce) lds_copy4(js.sigma[j] + (int64_t)g[k] * js.ld_sigma[j], sink);
+        }
+    }
 }
 
 // n (<= N) 8-byte entries from src to dst (both 16-byte aligned); lane l

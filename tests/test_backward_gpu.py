@@ -142,6 +142,22 @@ def test_backward_central_differences(F, name):
     assert err <= 1e-6
 
 
+@pytest.mark.parametrize("name", ["star_dim_root", "chain4", "star_wide_dimroot"])
+def test_backward_fused_join_same_gradient(F, name):
+    """R from a forward pass that reads the joined heads in place, and the
+    gradients behind it, equal those of a plan that always stores them, bit
+    for bit."""
+    import torch
+    inst = CASES[name]()
+    W = torch.as_tensor(_weighted(inst.n, 11))
+    _say(f"[backward-fused-join] case={name}")
+    g1, R1, _ = gpu_grads(F, inst, lambda R: (R * W.to(R.device)).sum())
+    g2, R2, _ = gpu_grads(F, inst, lambda R: (R * W.to(R.device)).sum(), separate_join=True)
+    assert np.array_equal(R1, R2)
+    for a, b in zip(g1, g2):
+        assert np.array_equal(a, b)
+
+
 def test_backward_split_tiles_same_gradient(F):
     import torch
     inst = CASES["two_rel_zipf"]()

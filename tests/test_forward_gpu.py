@@ -60,6 +60,9 @@ CASES = {
     "two_rel_zipf": lambda: synth.two_relation(10, 20000, 20000, 16, 16, 200, dist="zipf"),
     "two_rel_int64": lambda: synth.two_relation(11, 3000, 2000, 3, 4, 50, key_dtype=np.int64),
     "wide_root_40": lambda: synth.random_star(12, 5, 4000, 80, 8),
+    # a non-root relation with five children: its joined heads are stored
+    # (process_and_join_children on its own), not read in place
+    "star_dim_root_6": lambda: synth.random_star(23, 7, 2000, 30, 2, root=1),
     # more than 40 columns: wide head/tail tasks in column chunks, the
     # cooperative dense TSQR (two, three and four column groups)
     "chain4_wide_64": lambda: synth.random_chain(16, 4, 120, 16, 12),
@@ -119,6 +122,18 @@ def test_forward_staged_tiles(F, oracle_lib, name, waves):
     err = _relf(R, ref)
     _say(f"[forward-staged] case={name} waves={waves} join_rows={plan.join_rows:.0f} rel_err={err:.3e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("name", ["star_dim_root", "chain4_zipf", "star_wide_dimroot_100", "chain4_wide_64"])
+def test_fused_join_matches_separate_join(F, name):
+    """The first project-away level reads the joined heads in place; storing
+    them first (separate_join) computes the same products in the same order,
+    so R is bit for bit the same."""
+    inst = CASES[name]()
+    _say(f"[fused-join] case={name}")
+    R1, _, _ = gpu_r(F, inst)
+    R2, _, _ = gpu_r(F, inst, separate_join=True)
+    assert np.array_equal(R1, R2)
 
 
 def test_forward_deterministic(F):
