@@ -442,7 +442,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
     double *rw = lds + wib * r_slice_doubles<NB, ROT>();
     r_zero<NB, ROT>(rw, lane);
     const int64_t n_data = a.tiles_per_wave;
-    const int64_t n_iter = n_data + ((wib == 0) ? merge_tiles<NB, RPL>() : 0);
+    // only wave 0 of the workgroup has rows: nothing to merge (it still
+    // meets the others at the one barrier, after its tiles)
+    const bool merge = a.rows - (int64_t)blockIdx.x * kWavesPerBlock * a.tiles_per_wave * T > a.tiles_per_wave * T;
+    const int64_t n_iter = n_data + ((wib == 0 && merge) ? merge_tiles<NB, RPL>() : 0);
     for (int64_t it = 0; it < n_iter; ++it) {
         double x[RPL][NB];
         if (it >= n_data) {
@@ -460,10 +463,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
         }
         qr_step<NB, RPL, ROT>(x, rw, a.n);
     }
-    if (wib > 0) {
-        __syncthreads();
-        return;
-    }
+    if (wib > 0 || !merge) __syncthreads();
+    if (wib > 0) return;
     if (lane >= a.n) return;
     if (a.waves == 1 && a.final_r) {
         const double sg = (rw[lane * NB + lane] < 0.0) ? -1.0 : 1.0;

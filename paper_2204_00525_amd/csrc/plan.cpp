@@ -853,7 +853,10 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     const int64_t wpb = dense_waves_per_block(n);
     const int64_t step_rows = wpb * dt;
     const bool wide = n > kFusedMaxCols;
-    const int64_t mid_tpw = wide ? 4 : 1, final_tiles = wide ? 8 : 4;
+    // narrow: one tile per wave at every level (each level costs the latency
+    // of two tile steps, data then merge), and a last level of at most one
+    // tile per wave; a last level of one tile needs no merge at all
+    const int64_t mid_tpw = wide ? 4 : 1, final_tiles = wide ? 8 : 1;
     int64_t rows = srow;
     int64_t maxnext = 0;
     while (true) {
