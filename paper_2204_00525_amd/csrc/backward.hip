@@ -17,9 +17,62 @@ namespace figaro {
 namespace {
 
 // K = R^{-1} Phi R^{-T} with Phi = tril(M) + tril(M,-1)^T, M = R triu(dR)^T.
-// One workgroup of 128 threads, n <= 128; thread t owns column t.  R is
-// staged in LDS; W (global, n x n) holds Y = R^{-1} Phi between the two
-// triangular solves.
+// n <= 64: everything in LDS.  R and triu(dR) are staged; the n^2 entries of
+// Phi are spread over the 256 threads; then thread t < n solves R Y[:, t] =
+// Phi[:, t] in place and R K[:, t] = Y[t, :]^T (back substitutions, the
+// operands in LDS, so only the FMA chain is sequential).
+constexpr int kAdjSmall = 64;
+__global__ __launch_bounds__(256) void k_qr_adjoint_small(const double *R, const double *dR, int n, double *K,
+                                                          int32_t *status) {
+    __shared__ double sR[kAdjSmall][kAdjSmall + 1];
+    __shared__ double sD[kAdjSmall][kAdjSmall + 1];
+    __shared__ double sW[kAdjSmall][kAdjSmall + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        sR[r][c] = (c >= r) ? R[e] : 0.0;
+        sD[r][c] = (c >= r) ? dR[e] : 0.0;
+    }
+    __syncthreads();
+    // Phi[i][t] = M[a][b], a = max(i, t), b = min(i, t), M[a][b] = sum_{k >= a} R[a][k] dR[b][k]
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e % n, t = e / n;
+        const int a = (i >= t) ? i : t, b = (i >= t) ? t : i;
+        double m = 0.0;
+        for (int k = a; k < n; ++k) m = fma(sR[a][k], sD[b][k], m);
+        sW[i][t] = m;
+    }
+    __syncthreads();
+    if (tid < n) {
+        // Y[:, t] = R^{-1} Phi[:, t]
+        const int t = tid;
+        for (int i = n - 1; i >= 0; --i) {
+            double y = sW[i][t];
+            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], sW[k][t], y);
+            sW[i][t] = y / sR[i][i];
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
+        // K[:, t] = R^{-1} Y[t, :]^T, built in row t of sD (dR is no longer needed)
+        const int t = tid;
+        for (int i = n - 1; i >= 0; --i) {
+            double y = sW[t][i];
+            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], sD[t][k], y);
+            sD[t][i] = y / sR[i][i];
+        }
+        for (int i = 0; i < n; ++i) K[(int64_t)t * n + i] = sD[t][i];
+    }
+    if (tid == 0) {
+        int32_t singular = 0;
+        for (int i = 0; i < n; ++i) singular |= (sR[i][i] == 0.0) ? 1 : 0;
+        status[0] = singular;
+    }
+}
+
+// The same for n <= 128: one workgroup of 128 threads; thread t owns column
+// t.  R is staged in LDS; W (global, n x n) holds Y = R^{-1} Phi between the
+// two triangular solves.
 __global__ __launch_bounds__(kMaxCols) void k_qr_adjoint(const double *R, const double *dR, int n, double *K,
                                                          double *W, int32_t *status) {
     __shared__ double sR[kMaxCols][kMaxCols + 1];
@@ -326,7 +379,8 @@ hipError_t helmert_bwd_wide(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
 
 hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, double *W, int32_t *status,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(kMaxCols), 0, s, R, dR, (int)n, K, W, status);
+    if (n <= kAdjSmall) hipLaunchKernelGGL(k_qr_adjoint_small, dim3(1), dim3(256), 0, s, R, dR, (int)n, K, status);
+    else hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(kMaxCols), 0, s, R, dR, (int)n, K, W, status);
     return hipGetLastError();
 }
 
