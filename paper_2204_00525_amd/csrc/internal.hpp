@@ -257,6 +257,7 @@ int waves_per_block();                // waves per workgroup of the QR kernels
 struct Level {
     int64_t items = 0, npieces = 0, nchunks = 0;
     bool unit = false;
+    int32_t variant = 0;          // tile shape of the head/tail kernel at this level
     int32_t waves = 0;
     int64_t stack_row0 = 0;       // first stack row of this launch's R's
     int64_t r0_row0 = 0;          // first R0 row of this level

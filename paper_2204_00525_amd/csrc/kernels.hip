@@ -678,7 +678,7 @@ int nb_for(int ncols) {
 template <int NB, int V>
 struct Shape {
     static constexpr bool ROT = V == 1;
-    static constexpr int RPL = V == 2 ? (NB <= 8 ? 6 : NB <= 16 ? 3 : 1)
+    static constexpr int RPL = V == 2 ? (NB <= 8 ? 6 : NB <= 16 ? 2 : 1)
                                       : (NB <= 8 ? 8 : NB <= 16 ? 4 : !ROT ? 2 : 1);
     static constexpr int OCC = (V == 2 && NB <= 32) ? 2 : 1;
 };

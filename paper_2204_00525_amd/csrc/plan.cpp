@@ -181,8 +181,14 @@ void postorder(const figaro_plan_s *p, int v, std::vector<int32_t> &out) {
 //   group_off: [ngroups+1] item offsets of the groups (level 0)
 //   counts   : per-item counts (empty = every item counts 1, unit level 0)
 //   phi      : per-group tail scale
+//   tile     : items per chunk of the first level (the task's tile shape)
+// The upper levels are small and latency-bound: they take the shape with two
+// waves per SIMD (variant 2) and its smaller chunks, which doubles the waves
+// in flight (ncols <= 32; wider tasks keep the task's shape).
 figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::vector<int64_t> &group_off,
                          const std::vector<int64_t> &counts, const std::vector<double> &phi, int tile) {
+    const int up_variant = (T.ncols <= 32) ? 2 : T.variant;
+    const int tile_up = std::min(tile, tile_items_for(T.ncols, up_variant));
     const int64_t ngroups = (int64_t)group_off.size() - 1;
     // level state
     std::vector<int64_t> goff = group_off;      // group offsets over this level's items
@@ -193,6 +199,7 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
         Level L;
         L.items = nitems;
         L.unit = unit;
+        L.variant = level == 0 ? T.variant : up_variant;
         // chunks
         std::vector<int64_t> cs;
         cs.push_back(0);
@@ -203,13 +210,13 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
             int64_t cur = 0;       // items in the current chunk
             for (int64_t g = 0; g < ngroups; ++g) {
                 int64_t gs = goff[g], ge = goff[g + 1], sz = ge - gs;
-                if (sz > tile) {
+                if (sz > tile_up) {
                     if (cur > 0) { cs.push_back(gs); cur = 0; }
-                    for (int64_t s = gs + tile; s < ge; s += tile) cs.push_back(s);
+                    for (int64_t s = gs + tile_up; s < ge; s += tile_up) cs.push_back(s);
                     cs.push_back(ge);
                     cur = 0;
                 } else {
-                    if (cur + sz > tile) { cs.push_back(gs); cur = 0; }
+                    if (cur + sz > tile_up) { cs.push_back(gs); cur = 0; }
                     cur += sz;
                 }
             }

@@ -138,7 +138,7 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
             const double flops = fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
             ProfScope ps(p, s, kind, bytes, flops);
             if (!wide) {
-                FIGARO_TRY(launch_helmert(a, L.unit, fold, T.variant, s));
+                FIGARO_TRY(launch_helmert(a, L.unit, fold, L.variant, s));
             } else {
                 // column chunks: the tails of every column depend on that
                 // column only; the first chunk also writes the zeros of the
@@ -151,7 +151,7 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
                     ac.pieces_out = L.d_pieces + (int64_t)c0 * L.npieces;
                     for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint8_t)T.cols[c0 + c];
                     if (c0 > 0) ac.other_cols[0] = ac.other_cols[1] = 0;
-                    FIGARO_TRY(launch_helmert(ac, L.unit, false, T.variant, s));
+                    FIGARO_TRY(launch_helmert(ac, L.unit, false, L.variant, s));
                 }
             }
         }
