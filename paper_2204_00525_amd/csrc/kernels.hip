@@ -108,11 +108,23 @@ __device__ __forceinline__ double recip(double x) {
     return fma(r, e, r);
 }
 
+// Reciprocal square root by the hardware estimate refined with two Newton
+// iterations (y <- y + y (1/2 - (s/2) y^2)); s is a positive normal number.
+__device__ __forceinline__ double rsqrt_refined(double s) {
+    double y = __builtin_amdgcn_rsq(s);
+    const double h = 0.5 * s;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
 // Householder reflector of one column of [R; X] (LAPACK dlarfg form): with p
 // the pivot R_jj and x2 = ||X_j||^2 > 0,
 //   beta = -sign(p) sqrt(p^2 + x2),  tau = (beta - p) / beta,  scale = 1 / (p - beta),
 // so that v = [1; X_j * scale] and H = I - tau v v^T.  For x2 = 0 the
-// reflector is the identity (tau = 0) and R_jj stays p.  Branch-free.
+// reflector is the identity (tau = 0) and R_jj stays p.  Branch-free.  One
+// reciprocal square root gives both |beta| = s / sqrt(s) and 1 / beta.
 struct Reflector {
     double tau, scale, ts, rjj;
 };
@@ -121,13 +133,14 @@ __device__ __forceinline__ Reflector reflector(double p, double x2) {
     // act = 1 for x2 > 0, else 0; every quantity it multiplies is finite, so
     // multiplying by it replaces the selects
     const double act = (x2 > 0.0) ? 1.0 : 0.0;
-    const double nrm = sqrt(fma(p, p, x2));
-    const double beta = (p >= 0.0) ? -nrm : nrm;
     // (exact: one of the two terms of each sum is zero)
     const double off = 1.0 - act;
+    const double s = fma(act, fma(p, p, x2), off);   // p^2 + x2, or 1
+    const double r = rsqrt_refined(s);
+    const double nrm = s * r;
+    const double beta = (p >= 0.0) ? -nrm : nrm;
+    const double inv_b = (p >= 0.0) ? -r : r;        // 1 / beta
     const double den = fma(act, p - beta, off);      // p - beta (|p - beta| >= nrm), or 1
-    const double bden = fma(act, beta, off);         // beta, or 1
-    const double inv_b = recip(bden);
     Reflector h;
     h.scale = recip(den);
     h.tau = -act * den * inv_b;                      // (beta - p) / beta, or 0
