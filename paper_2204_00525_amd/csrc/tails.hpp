@@ -142,20 +142,12 @@ __device__ __forceinline__ void tile_load(const TailSrc &a, int64_t cs, int64_t 
     if constexpr (JOIN) {
         join_load<NB, RPL>(*js, col0, a.ncols, base, ti.valid, cs, x);
     } else {
-        // every lane loads (clamped column and row: the loads need no
-        // branches and are all in flight together), then selects
-        int64_t row[RPL];
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) row[k] = ti.valid[k] ? base + k : cs;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
             const bool live = c < a.ncols;
             const double *col = a.in + (int64_t)(live ? c : 0) * a.ld_in;
 #pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const double v = col[row[k]];
-                x[k][c] = (live && ti.valid[k]) ? v : 0.0;
-            }
+            for (int k = 0; k < RPL; ++k) x[k][c] = (live && ti.valid[k]) ? col[base + k] : 0.0;
         }
     }
 #pragma unroll
