@@ -123,7 +123,8 @@ __global__ __launch_bounds__(kMaxCols) void k_qr_adjoint(const double *R, const 
 // row-major directly).
 template <int NB, int RPL>
 __device__ __forceinline__ void bwd_finish(const HelmertBwdArgs &a, double (&x)[RPL][NB], const TileItems<RPL> &ti,
-                                           int64_t cs, int64_t ce, int lane, int oc0, int nout, double *st) {
+                                           int64_t cs, int64_t ce, int lane, int oc0, int nout, double *st,
+                                           double *rs = nullptr) {
     double agg[NB];
     bool lane_last = false;
 #pragma unroll
@@ -158,6 +159,25 @@ __device__ __forceinline__ void bwd_finish(const HelmertBwdArgs &a, double (&x)[
         }
     }
     const int64_t nitems = ce - cs;
+    if (a.gout_rowmajor && rs && oc0 == 0 && nout == NB && a.ld_gout == NB) {
+        // the tile's rows are one contiguous block of the row-major output:
+        // build it in the wave's LDS slice (each lane's RPL rows, lanes
+        // padded by one double against bank conflicts), then store it
+        // linearly, 64 consecutive doubles per store instruction (same wave:
+        // LDS accesses complete in order, no barrier needed)
+        constexpr int LR = RPL * NB, LS = LR + 1;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) rs[lane * LS + k * NB + c] = x[k][c];
+        const int total = (int)nitems * NB;
+        double *dst = a.gout + cs * a.ld_gout;
+        for (int e = lane; e < total; e += 64) {
+            const int l = e / LR;
+            dst[e] = rs[l * LS + (e - l * LR)];
+        }
+        return;
+    }
     if (a.gout_rowmajor) {
         // rows of the lane's items are contiguous in a row-major output
         const int64_t base = cs + (int64_t)lane * RPL;
@@ -216,10 +236,13 @@ __device__ __forceinline__ void tile_times_k(const double (&x)[RPL][NB], const d
 // independent here (no accumulation), one or more per wave.  The block of K
 // that the level's rows touch is staged in LDS; the tails are recomputed
 // (tile_tails) and dT = T K_blk goes through bwd_finish.
-template <int NB, int RPL, int MODE>
+// ROWS: the output is row-major with exactly NB columns (the gradient of
+// joined heads), written through a row-major tile in LDS.
+template <int NB, int RPL, int MODE, bool ROWS>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
     __shared__ double sK[NB * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[c]], zero outside ncols
     __shared__ double stage[kWavesPerBlock * 64 * RPL];   // per-wave store staging
+    __shared__ double rstage[ROWS ? kWavesPerBlock * 64 * (RPL * NB + 1) : 1];   // per-wave row-major tile
     for (int i = threadIdx.x; i < NB * NB; i += blockDim.x) {
         const int e = i / NB, c = i % NB;
         sK[i] = (e < a.ncols && c < a.ncols) ? a.K[(int64_t)a.colmap[c] * a.n_total + a.colmap[e]] : 0.0;
@@ -246,7 +269,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
 #pragma unroll
             for (int c = 0; c < NB; ++c) g[k][c] = 0.0;
         tile_times_k<NB, RPL>(x, sK, koff, g);
-        bwd_finish<NB, RPL>(a, g, ti, cs, ce, lane, 0, a.ncols, st);
+        bwd_finish<NB, RPL>(a, g, ti, cs, ce, lane, 0, a.ncols, st,
+                            ROWS ? rstage + (threadIdx.x >> 6) * (64 * (RPL * NB + 1)) : nullptr);
     }
 }
 
@@ -362,8 +386,14 @@ template <int NB>
 hipError_t helmert_bwd_nb(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
     constexpr int RPL = (NB == 8) ? 8 : (NB == 16 ? 4 : 2);
     dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock), block(64 * kWavesPerBlock);
-    if (unit) hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 0>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 1>), grid, block, 0, s, a);
+    const bool rows = a.gout_rowmajor && a.ncols == NB && a.ld_gout == NB;
+    if (rows) {
+        if (unit) hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 0, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 1, true>), grid, block, 0, s, a);
+    } else {
+        if (unit) hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 0, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_helmert_bwd<NB, RPL, 1, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
