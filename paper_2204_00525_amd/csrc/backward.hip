@@ -318,20 +318,23 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd_wide(Helmer
     }
 }
 
-// Backward of process_and_join_children.  Part 0: one thread per (own
-// column c, key group g): dOwn[c][g] = ds[g][own_pos + c] * own_mult[g].
+// Backward of process_and_join_children.  Part 0: one thread per (key
+// group g, own column c), c fastest, so a wave reads whole row segments of
+// the row-major ds: dOwn[c][g] = ds[g][own_pos + c] * own_mult[g].
 // Part 1 + j: one thread per (group q of child j, column c): the sum over
 // the parent key groups g with cidx_j[g] = q (the plan's inverse index, a
 // fixed order, so the result is deterministic) of ds[g][colpos_j[c]] *
-// mult_j[g].  ds is row-major, so the threads of one q read one row.
+// mult_j[g].  ds is row-major, so the threads of one q read one row.  The
+// parts are consecutive ranges of blocks (a one-dimensional grid).
 __global__ void k_join_bwd(JoinBwdArgs a) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int part = blockIdx.y;
+    int part = 0;
+    while (part <= a.nchildren && (int64_t)blockIdx.x >= a.part_block0[part + 1]) ++part;
+    const int64_t idx = ((int64_t)blockIdx.x - a.part_block0[part]) * blockDim.x + threadIdx.x;
     if (part == 0) {
-        if (a.own_cols <= 0 || a.groups <= 0) return;
-        const int c = (int)(idx / a.groups);
-        const int64_t g = idx - (int64_t)c * a.groups;
-        if (c >= a.own_cols) return;
+        if (a.own_cols <= 0) return;
+        const int64_t g = idx / a.own_cols;
+        const int c = (int)(idx - g * a.own_cols);
+        if (g >= a.groups) return;
         a.dOwn[(int64_t)c * a.ld_own + g] = a.ds[g * a.ld_ds + a.own_pos + c] * a.own_mult[g];
         return;
     }
@@ -424,14 +427,18 @@ hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s)
     }
 }
 
-hipError_t launch_join_bwd(const JoinBwdArgs &a, hipStream_t s) {
-    int64_t mx = a.groups * std::max(a.own_cols, 0);
-    for (int j = 0; j < a.nchildren; ++j) mx = std::max(mx, a.child_groups[j] * a.child_cols[j]);
-    if (mx <= 0) return hipSuccess;
+hipError_t launch_join_bwd(const JoinBwdArgs &a_in, hipStream_t s) {
+    JoinBwdArgs a = a_in;
     const int bs = 256;
-    const int64_t blocks = (mx + bs - 1) / bs;
+    // part p covers blocks part_block0[p] .. part_block0[p + 1] - 1
+    a.part_block0[0] = 0;
+    a.part_block0[1] = (a.groups * std::max(a.own_cols, 0) + bs - 1) / bs;
+    for (int j = 0; j < a.nchildren; ++j)
+        a.part_block0[j + 2] = a.part_block0[j + 1] + (a.child_groups[j] * a.child_cols[j] + bs - 1) / bs;
+    const int64_t blocks = a.part_block0[a.nchildren + 1];
+    if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_join_bwd, dim3((unsigned)blocks, 1 + a.nchildren), dim3(bs), 0, s, a);
+    hipLaunchKernelGGL(k_join_bwd, dim3((unsigned)blocks), dim3(bs), 0, s, a);
     return hipGetLastError();
 }
 

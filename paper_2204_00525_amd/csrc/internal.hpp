@@ -201,6 +201,7 @@ struct JoinBwdArgs {
     const int64_t *inv_off[kMaxChildren];   // [child groups + 1]
     const int32_t *inv_idx[kMaxChildren];   // parent key groups sorted by child group
     const double *mult[kMaxChildren];
+    int64_t part_block0[kMaxChildren + 2];   // first block of every part (set by the launcher)
 };
 
 // Backward of the root heads: row_g = s_g / sqrt(c_g), d row_g = row_g K,
