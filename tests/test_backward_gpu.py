@@ -58,6 +58,10 @@ CASES = {
     # and n = 100 (cooperative dense TSQR, QR adjoint beyond 64 columns)
     "chain4_wide": lambda: synth.random_chain(16, 4, 40, 16, 8),
     "star_wide_dimroot": lambda: synth.random_star(17, 5, 300, 30, 20, root=3),
+    # joined heads of exactly 8 and 16 columns under a dimension root: their
+    # row-major gradient goes out as one contiguous block per tile
+    "star_dimroot_rows8": lambda: synth.random_star(30, 3, 400, 25, 4, root=1),
+    "star_dimroot_rows16": lambda: synth.random_star(31, 3, 400, 25, 8, root=1),
 }
 
 
