@@ -98,7 +98,9 @@ struct HelmertArgs {
 };
 
 // Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
-// `waves` workgroups, 4 waves each, tiles_per_wave tiles per wave) writes its
+// `waves` workgroups; n <= 32: 4 waves on separate tiles, tiles_per_wave
+// tiles per wave; n > 32: waves sharing each tile, tiles_per_wave tiles per
+// workgroup) writes its
 // R (n rows) to `out` rows b*n, or the final R (sign-normalised) to `final_r`
 // when there is a single workgroup.
 struct DenseArgs {
@@ -248,6 +250,7 @@ int tile_items_for(int ncols, int variant);   // items per chunk of the register
 int num_variants();                           // number of register-tile kernel variants
 int dense_tile_rows_for(int ncols, int variant);   // rows per tile of the dense kernel
 int dense_waves_per_block(int ncols);   // waves of a workgroup that fold separate tiles
+bool dense_coop(int ncols);            // dense steps share each tile among a workgroup's waves
 int waves_per_block();                // waves per workgroup of the QR kernels
 
 // ---------------------------------------------------------------------------

@@ -6,7 +6,10 @@
 //              project_away_join_attributes of Algorithm 3, and the leaf of
 //              the post-processing TSQR of the section "Post-processing")
 //  k_dense   : wave-level Householder TSQR step over a dense stack of rows
-//              (the second post-processing step), final step sign-normalises
+//              (the second post-processing step, n <= 32), final step
+//              sign-normalises
+//  k_dense_coop : the same step for n > 32, the waves of a workgroup sharing
+//              each tile by column blocks
 //  k_join    : process_and_join_children of Algorithm 3 (gather + exact
 //              integer scale products)
 //  k_root    : the root's Data rows (heads) appended to the stack
@@ -492,26 +495,30 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
     }
 }
 
-// Dense TSQR step for wide matrices (kFusedMaxCols < n <= kMaxCols): the W
-// waves of a workgroup share each tile of kWideRows rows; wave w holds
-// columns [32w, 32w + 32) of the tile (kWideRPL rows per lane) and the same
-// columns of the workgroup's R (all n rows, row-major, in its LDS slice).
-// At the step of column j the wave that owns j forms the reflector from its
-// own column (kept at register column 0 by rotating its columns) and
-// publishes the column and the reflector's scalars through LDS; after one
-// barrier the waves to its right apply the reflector to their columns (and
-// their part of row j of R).  The scalars and the column are double-buffered,
-// so one barrier per column suffices.  Every wave runs the same number of
-// steps and barriers.  Workgroup b folds rows [b W', (b+1) W'), W' =
-// tiles_per_wave * kWideRows, into one R; the single workgroup of the last
-// level sign-normalises it.
+// Cooperative dense TSQR step (n > 32): the W waves of a workgroup share
+// each tile of kCoopRows rows; wave w holds columns [CW w, CW w + CW) of the
+// tile (kCoopRPL rows per lane) and the same columns of the workgroup's R
+// (all n rows, row-major, in its LDS slice).  CW is 8 for n <= 40 (W = 5)
+// and 32 for wider matrices.  At the step of column j the wave that owns j forms
+// the reflector from its own column (kept at register column 0 by rotating
+// its columns) and publishes the column and the reflector's scalars through
+// LDS; after one barrier the waves to its right apply the reflector to their
+// columns (and their part of row j of R).  The scalars and the column are
+// double-buffered, so one barrier per column suffices.  Sharing the tile
+// spreads each column's cross-lane reductions over the waves, so a tile
+// step takes the latency of one column's reflector per column instead of
+// that of all its reductions.  Every wave runs the same number of steps and
+// barriers.  Workgroup b folds rows [b W', (b+1) W'), W' = tiles_per_wave *
+// kCoopRows, into one R; the single workgroup of the last level
+// sign-normalises it.
 constexpr int kWideCols = 32;
-constexpr int kWideRPL = 2;
-constexpr int kWideRows = 64 * kWideRPL;
+constexpr int kNarrowCols = 8;
+constexpr int kCoopRPL = 2;
+constexpr int kCoopRows = 64 * kCoopRPL;
 
-template <int W>
-__global__ __launch_bounds__(64 * W) void k_dense_wide(DenseArgs a) {
-    constexpr int CW = kWideCols, RPL = kWideRPL, T = kWideRows;
+template <int W, int CW>
+__global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
+    constexpr int RPL = kCoopRPL, T = kCoopRows;
     constexpr int NW = CW * W;                   // rows of an R slice
     constexpr int SL = (NW + 1) * CW;            // slice: NW rows + a spare row
     __shared__ double rsl[W * SL];
@@ -767,12 +774,16 @@ int tile_items_for(int ncols, int variant) {
     }
 }
 
+// n <= 32: one wave per tile measured faster (a 32-column cooperative step
+// costs about as much as a single wave's step, and the level tree is deeper)
+bool dense_coop(int ncols) { return ncols > 32; }
+
 int dense_tile_rows_for(int ncols, int variant) {
-    return ncols > kFusedMaxCols ? kWideRows : tile_items_for(ncols, variant);
+    return dense_coop(ncols) ? kCoopRows : tile_items_for(ncols, variant);
 }
 
 int dense_waves_per_block(int ncols) {
-    return ncols > kFusedMaxCols ? 1 : kWavesPerBlock;
+    return dense_coop(ncols) ? 1 : kWavesPerBlock;
 }
 int waves_per_block() { return kWavesPerBlock; }
 int num_variants() { return kVariants; }
@@ -792,22 +803,25 @@ hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int varian
 
 hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
     if (a.waves <= 0) return hipSuccess;
-    switch (nb_for(a.n)) {
-        case 8: return dense_v<8>(a, variant, s);
-        case 16: return dense_v<16>(a, variant, s);
-        case 32: return dense_v<32>(a, variant, s);
-        default:
-            if (a.n <= kFusedMaxCols) return variant == 1 ? dense_nb<40, 1>(a, s) : dense_nb<40, 0>(a, s);
-            if (a.n > kMaxCols) return hipErrorInvalidValue;
-            {
-                const int w = (a.n + kWideCols - 1) / kWideCols;
-                dim3 grid(a.waves);
-                if (w == 2) hipLaunchKernelGGL(k_dense_wide<2>, grid, dim3(128), 0, s, a);
-                else if (w == 3) hipLaunchKernelGGL(k_dense_wide<3>, grid, dim3(192), 0, s, a);
-                else hipLaunchKernelGGL(k_dense_wide<4>, grid, dim3(256), 0, s, a);
-            }
-            return hipGetLastError();
+    if (a.n > kMaxCols) return hipErrorInvalidValue;
+    if (!dense_coop(a.n)) {
+        switch (nb_for(a.n)) {
+            case 8: return dense_v<8>(a, variant, s);
+            case 16: return dense_v<16>(a, variant, s);
+            default: return dense_v<32>(a, variant, s);
+        }
     }
+    const dim3 grid(a.waves);
+    if (a.n <= kFusedMaxCols) {
+        static_assert(kFusedMaxCols <= 5 * kNarrowCols, "five column blocks cover a narrow stack");
+        hipLaunchKernelGGL((k_dense_coop<5, kNarrowCols>), grid, dim3(320), 0, s, a);
+    } else {
+        const int w = (a.n + kWideCols - 1) / kWideCols;
+        if (w == 2) hipLaunchKernelGGL((k_dense_coop<2, kWideCols>), grid, dim3(128), 0, s, a);
+        else if (w == 3) hipLaunchKernelGGL((k_dense_coop<3, kWideCols>), grid, dim3(192), 0, s, a);
+        else hipLaunchKernelGGL((k_dense_coop<4, kWideCols>), grid, dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_join(const JoinArgs &a, hipStream_t s) {
