@@ -21,7 +21,7 @@ def _relf(a, b):
 
 
 @pytest.mark.parametrize("variant", [0, 1, 2])
-@pytest.mark.parametrize("n", [1, 5, 8, 13, 16, 24, 32, 40, 41, 64, 65, 100, 128])
+@pytest.mark.parametrize("n", [1, 5, 8, 13, 16, 24, 32, 35, 40, 41, 64, 65, 100, 128])
 def test_single_workgroup_matches_householder(F, oracle_lib, n, variant):
     import torch
     tpw = 2
@@ -35,7 +35,7 @@ def test_single_workgroup_matches_householder(F, oracle_lib, n, variant):
     assert _relf(R, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [7, 16, 32, 48, 96, 128])
+@pytest.mark.parametrize("n", [7, 16, 32, 37, 48, 96, 128])
 def test_many_workgroups_preserve_gram(F, oracle_lib, n):
     import torch
     wg = 9
@@ -50,12 +50,17 @@ def test_many_workgroups_preserve_gram(F, oracle_lib, n):
     assert _relf(S.T @ S, Ghi + Glo) <= 1e-13
 
 
-def test_rank_deficient_and_zero_columns(F, oracle_lib):
+@pytest.mark.parametrize("n,rows", [(10, 300), (40, 250)])
+def test_rank_deficient_and_zero_columns(F, oracle_lib, n, rows):
     import torch
     rng = np.random.default_rng(3)
-    A = rng.standard_normal((300, 10))
+    A = rng.standard_normal((rows, n))
     A[:, 3] = 0.0
     A[:, 7] = 2.0 * A[:, 1]
+    if n > 32:
+        # the same inside the last column block of the shared-tile step
+        A[:, 35] = 0.0
+        A[:, 38] = -A[:, 33]
     R = F.debug_dense_step(torch.as_tensor(A).cuda(), 1, 2, 0).cpu().numpy()
     assert np.all(np.isfinite(R))
     Ghi, Glo = oracle_lib.gram_ld(np.asfortranarray(A))
