@@ -98,8 +98,8 @@ struct HelmertArgs {
 };
 
 // Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
-// `waves` workgroups; n <= 32: 4 waves on separate tiles, tiles_per_wave
-// tiles per wave; n > 32: waves sharing each tile, tiles_per_wave tiles per
+// `waves` workgroups; n <= 16: 4 waves on separate tiles, tiles_per_wave
+// tiles per wave; n > 16: waves sharing each tile, tiles_per_wave tiles per
 // workgroup) writes its
 // R (n rows) to `out` rows b*n, or the final R (sign-normalised) to `final_r`
 // when there is a single workgroup.

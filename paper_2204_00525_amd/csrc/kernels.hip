@@ -6,9 +6,9 @@
 //              project_away_join_attributes of Algorithm 3, and the leaf of
 //              the post-processing TSQR of the section "Post-processing")
 //  k_dense   : wave-level Householder TSQR step over a dense stack of rows
-//              (the second post-processing step, n <= 32), final step
+//              (the second post-processing step, n <= 16), final step
 //              sign-normalises
-//  k_dense_coop : the same step for n > 32, the waves of a workgroup sharing
+//  k_dense_coop : the same step for n > 16, the waves of a workgroup sharing
 //              each tile by column blocks
 //  k_join    : process_and_join_children of Algorithm 3 (gather + exact
 //              integer scale products)
@@ -495,13 +495,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
     }
 }
 
-// Cooperative dense TSQR step (n > 32): the W waves of a workgroup share
+// Cooperative dense TSQR step (n > 16): the W waves of a workgroup share
 // each tile of kCoopRows rows; wave w holds columns [CW w, CW w + CW) of the
 // tile (kCoopRPL rows per lane) and the same columns of the workgroup's R
-// (all n rows, row-major, in its LDS slice).  CW is 8 for n <= 40 (W = 5)
-// and 32 for wider matrices.  At the step of column j the wave that owns j forms
-// the reflector from its own column (kept at register column 0 by rotating
-// its columns) and publishes the column and the reflector's scalars through
+// (all n rows, row-major, in its LDS slice).  CW is 8 for n <= 40 (W =
+// ceil(n / 8)) and 32 for wider matrices.  At the step of column j the wave
+// that owns j forms the reflector from its own column (for CW = 32 kept at
+// register column 0 by rotating its columns; for CW = 8 the column loop is
+// unrolled within the block, so the owner works on the columns it still
+// holds in place) and publishes the column and the reflector's scalars through
 // LDS; after one barrier the waves to its right apply the reflector to their
 // columns (and their part of row j of R).  The scalars and the column are
 // double-buffered, so one barrier per column suffices.  Sharing the tile
@@ -515,6 +517,77 @@ constexpr int kWideCols = 32;
 constexpr int kNarrowCols = 8;
 constexpr int kCoopRPL = 2;
 constexpr int kCoopRows = 64 * kCoopRPL;
+
+// One column step of the shared-tile kernel with the column's place in its
+// block (JL) known at compile time (narrow blocks): the owner reduces only
+// the JL..CW-1 columns it still holds and reads its registers in place, with
+// no rotation.  j = o CW + JL >= n is skipped by every wave alike.
+template <int W, int CW, int RPL, int JL>
+__device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, double (*xb)[64 * RPL],
+                                            double (*sc)[4], int wib, int o, int n, int lane) {
+    const int j = o * CW + JL;
+    if (j >= n) return;
+    const int slot = j & 1;
+    if (wib == o) {
+        constexpr int C = CW - JL;
+        double d[C], p[C];
+#pragma unroll
+        for (int k = 0; k < C; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc = fma(x[r][JL], x[r][JL + k], acc);
+            d[k] = acc;
+            p[k] = rw[j * CW + JL + k];
+        }
+        wave_sum_batch<C>(d);
+        const Reflector h = reflector(p[0], d[0]);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) xb[slot][lane * RPL + r] = x[r][JL];
+        sc[slot][0] = h.scale;
+        sc[slot][1] = h.ts;
+        sc[slot][2] = h.tau;
+#pragma unroll
+        for (int k = 1; k < C; ++k) {
+            const double w = fma(h.scale, d[k], p[k]);
+            const double g = h.ts * w;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) x[r][JL + k] = fma(-g, x[r][JL], x[r][JL + k]);
+            rw[j * CW + JL + k] = fma(-h.tau, w, p[k]);
+        }
+        rw[j * CW + JL] = h.rjj;
+    }
+    __syncthreads();
+    if (wib > o) {
+        double xj[RPL], d[CW], p[CW];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) xj[r] = xb[slot][lane * RPL + r];
+        const double scale = sc[slot][0], ts = sc[slot][1], tau = sc[slot][2];
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) acc = fma(xj[r], x[r][k], acc);
+            d[k] = acc;
+            p[k] = rw[j * CW + k];
+        }
+        wave_sum_batch<CW>(d);
+#pragma unroll
+        for (int k = 0; k < CW; ++k) {
+            const double w = fma(scale, d[k], p[k]);
+            const double g = ts * w;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, xj[r], x[r][k]);
+            rw[j * CW + k] = fma(-tau, w, p[k]);
+        }
+    }
+}
+
+template <int W, int CW, int RPL, int... JLs>
+__device__ __forceinline__ void coop_block(double (&x)[RPL][CW], double *rw, double (*xb)[64 * RPL],
+                                           double (*sc)[4], int wib, int o, int n, int lane,
+                                           std::integer_sequence<int, JLs...>) {
+    (coop_column<W, CW, RPL, JLs>(x, rw, xb, sc, wib, o, n, lane), ...);
+}
 
 template <int W, int CW>
 __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
@@ -539,6 +612,11 @@ __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
             const double *src = a.in + (int64_t)(live ? col : 0) * a.ld_in;
 #pragma unroll
             for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? src[base + k] : 0.0;
+        }
+        if constexpr (CW <= kNarrowCols) {
+            for (int o = 0; o < W; ++o)
+                coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, std::make_integer_sequence<int, CW>{});
+            continue;
         }
         for (int j = 0; j < n; ++j) {
             const int o = j / CW, jl = j - o * CW, slot = j & 1;
@@ -774,9 +852,7 @@ int tile_items_for(int ncols, int variant) {
     }
 }
 
-// n <= 32: one wave per tile measured faster (a 32-column cooperative step
-// costs about as much as a single wave's step, and the level tree is deeper)
-bool dense_coop(int ncols) { return ncols > 32; }
+bool dense_coop(int ncols) { return ncols > 16; }
 
 int dense_tile_rows_for(int ncols, int variant) {
     return dense_coop(ncols) ? kCoopRows : tile_items_for(ncols, variant);
@@ -807,14 +883,16 @@ hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
     if (!dense_coop(a.n)) {
         switch (nb_for(a.n)) {
             case 8: return dense_v<8>(a, variant, s);
-            case 16: return dense_v<16>(a, variant, s);
-            default: return dense_v<32>(a, variant, s);
+            default: return dense_v<16>(a, variant, s);
         }
     }
     const dim3 grid(a.waves);
     if (a.n <= kFusedMaxCols) {
         static_assert(kFusedMaxCols <= 5 * kNarrowCols, "five column blocks cover a narrow stack");
-        hipLaunchKernelGGL((k_dense_coop<5, kNarrowCols>), grid, dim3(320), 0, s, a);
+        const int w = (a.n + kNarrowCols - 1) / kNarrowCols;
+        if (w == 3) hipLaunchKernelGGL((k_dense_coop<3, kNarrowCols>), grid, dim3(192), 0, s, a);
+        else if (w == 4) hipLaunchKernelGGL((k_dense_coop<4, kNarrowCols>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_dense_coop<5, kNarrowCols>), grid, dim3(320), 0, s, a);
     } else {
         const int w = (a.n + kWideCols - 1) / kWideCols;
         if (w == 2) hipLaunchKernelGGL((k_dense_coop<2, kWideCols>), grid, dim3(128), 0, s, a);
