@@ -859,12 +859,12 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     const int64_t dt = dense_tile_rows_for(n, p->variant);
     const int64_t wpb = dense_waves_per_block(n);
     const int64_t step_rows = wpb * dt;
-    const bool wide = n > kFusedMaxCols, coop = dense_coop(n);
+    const bool wide = n > kFusedMaxCols;
     // n <= 16: one tile per wave at every level (each level costs the
     // latency of two tile steps, data then merge), and a last level of at
     // most one tile per wave; a last level of one tile needs no merge at all.
-    // Shared tiles (n > 16): a few tiles per workgroup at every level.
-    const int64_t mid_tpw = wide ? 4 : coop ? 2 : 1, final_tiles = wide ? 8 : coop ? 4 : 1;
+    // Shared tiles (n > 16, up to 40): the same, one shared step per level.
+    const int64_t mid_tpw = wide ? 4 : 1, final_tiles = wide ? 8 : 1;
     int64_t rows = srow;
     int64_t maxnext = 0;
     while (true) {
