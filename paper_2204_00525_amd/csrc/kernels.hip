@@ -498,10 +498,10 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 // Cooperative dense TSQR step (n > 16): the W waves of a workgroup share
 // each tile of kCoopRows rows; wave w holds columns [CW w, CW w + CW) of the
 // tile (kCoopRPL rows per lane) and the same columns of the workgroup's R
-// (all n rows, row-major, in its LDS slice).  CW is 8 for n <= 40 (W =
-// ceil(n / 8)) and 32 for wider matrices.  At the step of column j the wave
+// (all n rows, row-major, in its LDS slice).  CW is 4 for n <= 32 (W = 6 or
+// 8), 8 for n <= 40 (W = 5) and 32 for wider matrices.  At the step of column j the wave
 // that owns j forms the reflector from its own column (for CW = 32 kept at
-// register column 0 by rotating its columns; for CW = 8 the column loop is
+// register column 0 by rotating its columns; for CW <= 8 the column loop is
 // unrolled within the block, so the owner works on the columns it still
 // holds in place) and publishes the column and the reflector's scalars through
 // LDS; after one barrier the waves to its right apply the reflector to their
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
 #pragma unroll
             for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? src[base + k] : 0.0;
         }
-        if constexpr (CW <= kNarrowCols) {
+        if constexpr (CW <= kNarrowCols) {   // 4 or 8 columns per wave
             for (int o = 0; o < W; ++o)
                 coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, std::make_integer_sequence<int, CW>{});
             continue;
@@ -889,9 +889,9 @@ hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
     const dim3 grid(a.waves);
     if (a.n <= kFusedMaxCols) {
         static_assert(kFusedMaxCols <= 5 * kNarrowCols, "five column blocks cover a narrow stack");
-        const int w = (a.n + kNarrowCols - 1) / kNarrowCols;
-        if (w == 3) hipLaunchKernelGGL((k_dense_coop<3, kNarrowCols>), grid, dim3(192), 0, s, a);
-        else if (w == 4) hipLaunchKernelGGL((k_dense_coop<4, kNarrowCols>), grid, dim3(256), 0, s, a);
+        // up to 32 columns: 4 per wave (6 or 8 waves); above: 8 per wave
+        if (a.n <= 24) hipLaunchKernelGGL((k_dense_coop<6, 4>), grid, dim3(384), 0, s, a);
+        else if (a.n <= 32) hipLaunchKernelGGL((k_dense_coop<8, 4>), grid, dim3(512), 0, s, a);
         else hipLaunchKernelGGL((k_dense_coop<5, kNarrowCols>), grid, dim3(320), 0, s, a);
     } else {
         const int w = (a.n + kWideCols - 1) / kWideCols;
