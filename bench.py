@@ -385,8 +385,10 @@ def main():
         log("cpu baseline: oracle on a subsample")
         v, secs, Ms, rows = cpu_baseline(args.cpu_div)
         out["cpu_baseline"] = {"value": v, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+                               "host_cores": os.cpu_count(),
                                "sample": f"two-relation join / {args.cpu_div}: {Ms} tuples, {rows} join rows "
-                                         f"materialised, textbook Householder ({secs:.1f} s)"}
+                                         f"materialised, textbook Householder ({secs:.1f} s), one thread "
+                                         f"of the {os.cpu_count()} host cores"}
     print(json.dumps(out), flush=True)
 
 

@@ -506,7 +506,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 // holds in place) and publishes the column and the reflector's scalars through
 // LDS; after one barrier the waves to its right apply the reflector to their
 // columns (and their part of row j of R).  The scalars and the column are
-// double-buffered, so one barrier per column suffices.  Sharing the tile
+// double-buffered by the parity of a column step count that runs on across
+// tiles, so one barrier per column suffices.  Sharing the tile
 // spreads each column's cross-lane reductions over the waves, so a tile
 // step takes the latency of one column's reflector per column instead of
 // that of all its reductions.  Every wave runs the same number of steps and
@@ -524,10 +525,12 @@ constexpr int kCoopRows = 64 * kCoopRPL;
 // no rotation.  j = o CW + JL >= n is skipped by every wave alike.
 template <int W, int CW, int RPL, int JL>
 __device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, double (*xb)[64 * RPL],
-                                            double (*sc)[4], int wib, int o, int n, int lane) {
+                                            double (*sc)[4], int wib, int o, int n, int lane, int par) {
     const int j = o * CW + JL;
     if (j >= n) return;
-    const int slot = j & 1;
+    // buffer parity from a step count that runs on across tiles, so the
+    // next tile's first column never reuses the buffer of this tile's last
+    const int slot = (par + j) & 1;
     if (wib == o) {
         constexpr int C = CW - JL;
         double d[C], p[C];
@@ -584,9 +587,9 @@ __device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, do
 
 template <int W, int CW, int RPL, int... JLs>
 __device__ __forceinline__ void coop_block(double (&x)[RPL][CW], double *rw, double (*xb)[64 * RPL],
-                                           double (*sc)[4], int wib, int o, int n, int lane,
+                                           double (*sc)[4], int wib, int o, int n, int lane, int par,
                                            std::integer_sequence<int, JLs...>) {
-    (coop_column<W, CW, RPL, JLs>(x, rw, xb, sc, wib, o, n, lane), ...);
+    (coop_column<W, CW, RPL, JLs>(x, rw, xb, sc, wib, o, n, lane, par), ...);
 }
 
 template <int W, int CW>
@@ -613,13 +616,14 @@ __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
 #pragma unroll
             for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? src[base + k] : 0.0;
         }
+        const int par = (int)((it * n) & 1);
         if constexpr (CW <= kNarrowCols) {   // 4 or 8 columns per wave
             for (int o = 0; o < W; ++o)
-                coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, std::make_integer_sequence<int, CW>{});
+                coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, par, std::make_integer_sequence<int, CW>{});
             continue;
         }
         for (int j = 0; j < n; ++j) {
-            const int o = j / CW, jl = j - o * CW, slot = j & 1;
+            const int o = j / CW, jl = j - o * CW, slot = (par + j) & 1;
             if (wib == o) {
                 // register column k holds local column jl + k
                 double d[CW], p[CW];

@@ -29,7 +29,7 @@ from typing import List, Optional
 import numpy as np
 
 __all__ = [
-    "Rel", "Instance", "config1", "config2", "config3", "config5_instance",
+    "Rel", "Instance", "config1", "config2", "config3", "config5_instance", "config5_params", "config5_sample",
     "config5", "cartesian_uniform", "appendix_a", "paper_fig3", "random_chain",
     "random_star", "two_relation", "zipf_probs",
 ]
@@ -159,6 +159,27 @@ def config3(seed: int = 1003, div: int = 1) -> Instance:
     return Instance(name, rels, {"seed": seed, "div": div, "scales": scales})
 
 
+def _config5_draw(i: int):
+    """The instance-level draws of config5_instance(i), in its draw order;
+    returns the generator positioned after them."""
+    rng = np.random.default_rng(5000 + i)
+    topology = "chain" if rng.random() < 0.5 else "star"
+    r = int(rng.integers(2, 5))
+    m = np.floor(10.0 ** rng.uniform(3.0, 6.0, r)).astype(np.int64)
+    n = rng.integers(4, 33, r)
+    dist = "zipf" if rng.random() < 0.5 else "uniform"
+    return rng, topology, r, m, n, dist
+
+
+def config5_params(i: int) -> dict:
+    """Shape of instance i of the batched workload without drawing its keys
+    and values: topology, key distribution, relation count, rows and columns
+    per relation."""
+    _, topology, r, m, n, dist = _config5_draw(i)
+    return {"topology": topology, "dist": dist, "r": r, "rows": [int(x) for x in m],
+            "cols": [int(x) for x in n], "n": int(n.sum())}
+
+
 def config5_instance(i: int) -> Instance:
     """One instance of the batched workload (seed 5000+i).
 
@@ -171,12 +192,7 @@ def config5_instance(i: int) -> Instance:
     table with one foreign key per dimension; dimension j has a unique key per
     row (a permutation of 0..m_j-1); the fact's foreign keys are uniform over
     the dimension's keys or Zipf over its first min(1000, m_j) keys."""
-    rng = np.random.default_rng(5000 + i)
-    topology = "chain" if rng.random() < 0.5 else "star"
-    r = int(rng.integers(2, 5))
-    m = np.floor(10.0 ** rng.uniform(3.0, 6.0, r)).astype(np.int64)
-    n = rng.integers(4, 33, r)
-    dist = "zipf" if rng.random() < 0.5 else "uniform"
+    rng, topology, r, m, n, dist = _config5_draw(i)
     rels: List[Rel] = []
     if topology == "chain":
         for j in range(r):
@@ -212,6 +228,25 @@ def config5_instance(i: int) -> Instance:
             rels.append(Rel([j - 1], k[None, :], vals, 0, f"D{j}"))
     return Instance(f"config5_{i}", rels,
                     {"seed": 5000 + i, "topology": topology, "dist": dist})
+
+
+def config5_sample(per_cell: int = 3, seed: int = 2025):
+    """Seeded stratified sample of the 512 instances of the batched workload:
+    the instances are grouped by (topology, key distribution, number of
+    relations, column bucket n <= 32 / <= 64 / <= 96 / > 96), and from every
+    group up to `per_cell` ids are drawn without replacement with
+    numpy.random.default_rng(seed)."""
+    cells = {}
+    for i in range(512):
+        p = config5_params(i)
+        nb = 0 if p["n"] <= 32 else 1 if p["n"] <= 64 else 2 if p["n"] <= 96 else 3
+        cells.setdefault((p["topology"], p["dist"], p["r"], nb), []).append(i)
+    rng = np.random.default_rng(seed)
+    out = []
+    for key in sorted(cells):
+        ids = cells[key]
+        out += rng.choice(ids, size=min(per_cell, len(ids)), replace=False).tolist()
+    return sorted(int(i) for i in out)
 
 
 def config5(count: int = 512, start: int = 0) -> List[Instance]:

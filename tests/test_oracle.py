@@ -106,6 +106,82 @@ def test_join_matches_brute_force(oracle_lib, maker):
     assert _multiset(A) == _multiset(B)
 
 
+@pytest.mark.parametrize("maker", [
+    lambda: synth.paper_fig3(1),
+    lambda: synth.paper_fig3(2, m=(4, 7, 3, 3), dom=3),
+    lambda: synth.random_chain(3, 3, 6, 2, 3),
+    lambda: synth.random_chain(7, 4, 5, 1, 2, dist="zipf"),
+    lambda: synth.random_star(4, 3, 8, 3, 2, pk_dims=False, dom=3),
+    lambda: synth.random_star(9, 3, 9, 3, 2, root=1),
+    lambda: synth.cartesian_uniform(5, 3, 2, 4, 1),
+    lambda: synth.two_relation(14, 12, 9, 2, 1, 5),
+])
+def test_join_indices_pinned(oracle_lib, maker):
+    """join_indices against the definition of the natural join: its rows are
+    exactly the combinations of tuples that agree on every shared attribute
+    (brute force over all combinations), each once; and join() is the
+    per-relation gather values_i[:, idx_i] of those rows, in the same order."""
+    inst = maker()
+    if inst.name == "two_relation_uniform":
+        inst.rels[0].keys[0, :3] = 99      # dangling tuples take part in no row
+    idx = oracle_lib.join_indices(inst)
+    combos = oracle_lib.brute_join_rows(inst, list(range(inst.r)))
+    assert idx.shape == (inst.r, len(combos))
+    assert sorted(map(tuple, idx.T.tolist())) == sorted(combos)
+    A = oracle_lib.join(inst)
+    gathered = np.column_stack([inst.rels[i].values[:, idx[i]].T for i in range(inst.r)])
+    assert np.array_equal(A, gathered)
+
+
+def test_join_indices_planted_mistake_is_caught(oracle_lib):
+    """Plausible indexing mistakes fail the definition check above: one join
+    row repeated in place of another, or one relation's row index off by one
+    in a single join row."""
+    inst = synth.paper_fig3(2, m=(4, 7, 3, 3), dom=3)
+    combos = sorted(oracle_lib.brute_join_rows(inst, list(range(inst.r))))
+    idx = oracle_lib.join_indices(inst).copy()
+    assert idx.shape[1] >= 2
+    dup = idx.copy()
+    dup[:, 1] = dup[:, 0]
+    assert sorted(map(tuple, dup.T.tolist())) != combos
+    off = idx.copy()
+    off[1, 0] = (off[1, 0] + 1) % inst.rels[1].rows
+    assert sorted(map(tuple, off.T.tolist())) != combos
+
+
+def test_gram_relerr_exact_values(oracle_lib):
+    """gram_relerr = ||R^T R - G||_F / ||G||_F against values computed exactly
+    in integers: zero for G = R^T R, and the planted residual of a known
+    integer perturbation E, also when E sits in the lo part of a hi + lo
+    pair (2^-40 E, exactly representable in long double next to G)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(31)
+    n = 6
+    Ri = np.triu(rng.integers(-9, 10, (n, n)))
+    Ri[np.diag_indices(n)] = rng.integers(1, 10, n)
+    Gi = Ri.T.astype(object) @ Ri.astype(object)
+    R = Ri.astype(np.float64)
+    G = np.array(Gi, dtype=np.float64)
+    zero = np.zeros((n, n))
+    assert oracle_lib.gram_relerr(R, G, zero) == 0.0
+    E = np.zeros((n, n), dtype=np.int64)
+    E[2, 4] = E[4, 2] = 3
+    E[0, 0] = -5
+    E[5, 1] = E[1, 5] = 7
+    Gp = Gi + E.astype(object)
+    expect = math.sqrt(Fraction(int(np.sum(E.astype(object) ** 2)), int(np.sum(Gp ** 2))))
+    got = oracle_lib.gram_relerr(R, np.array(Gp, dtype=np.float64), zero)
+    assert got > 0 and abs(got - expect) <= 1e-14 * expect
+    lo = np.ldexp(E.astype(np.float64), -40)
+    num = Fraction(int(np.sum(E.astype(object) ** 2)), 2 ** 80)
+    den = sum((Fraction(int(g)) + Fraction(int(e), 2 ** 40)) ** 2 for g, e in zip(Gi.ravel(), E.ravel()))
+    expect_lo = math.sqrt(num / den)
+    got_lo = oracle_lib.gram_relerr(R, G, lo)
+    assert abs(got_lo - expect_lo) <= 1e-12 * expect_lo
+    # a wrong factor (the transpose) is far off
+    assert oracle_lib.gram_relerr(R.T.copy(), G, zero) > 0.1
+
+
 def test_join_two_relation_size_closed_form(oracle_lib):
     inst = synth.config1()
     ks = np.bincount(inst.rels[0].keys[0], minlength=100)

@@ -99,3 +99,23 @@ def test_config2_join_size_exact(oracle_lib):
     ks = np.bincount(inst.rels[0].keys[0], minlength=1000).astype(object)
     kt = np.bincount(inst.rels[1].keys[0], minlength=1000).astype(object)
     assert plan.join_rows == float(sum(ks * kt))
+
+
+def test_config5_sample_covers_every_stratum():
+    """The parity sample of the batched workload has at least 64 instances and
+    contains every topology, key distribution, relation count and column
+    bucket of the 512."""
+    ids = synth.config5_sample()
+    assert len(ids) >= 64 and len(set(ids)) == len(ids)
+    def strata(i):
+        p = synth.config5_params(i)
+        nb = 0 if p["n"] <= 32 else 1 if p["n"] <= 64 else 2 if p["n"] <= 96 else 3
+        return p["topology"], p["dist"], p["r"], nb
+    everything = {strata(i) for i in range(512)}
+    got = {strata(i) for i in ids}
+    assert got == everything
+    # the draws of the shape parameters are those of the full instance
+    for i in ids[:5]:
+        inst = synth.config5_instance(i)
+        p = synth.config5_params(i)
+        assert [rel.rows for rel in inst.rels] == p["rows"] and inst.n == p["n"]
