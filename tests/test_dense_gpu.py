@@ -53,9 +53,10 @@ def test_many_workgroups_preserve_gram(F, oracle_lib, n):
     assert _relf(S.T @ S, Ghi + Glo) <= 1e-13
 
 
-@pytest.mark.parametrize("n,rows", [(10, 300), (23, 260), (29, 270), (40, 250)])
-def test_rank_deficient_and_zero_columns(F, oracle_lib, n, rows):
+@pytest.mark.parametrize("n", [10, 23, 29, 40])
+def test_rank_deficient_and_zero_columns(F, oracle_lib, n):
     import torch
+    rows = F.debug_dense_rows(n, 0, 2) - 7      # one workgroup, a ragged last tile
     rng = np.random.default_rng(3)
     A = rng.standard_normal((rows, n))
     A[:, 3] = 0.0
