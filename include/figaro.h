@@ -219,6 +219,23 @@ figaro_status figaro_r0(figaro_plan_t plan, const double *const *values, const i
                         double *R0, int64_t ld_r0, int32_t *block_of_row, hipStream_t stream);
 
 /*
+ * The post-processing QR (section "Post-processing") of a plain matrix: R
+ * of the rows x n FP64 matrix A (device, column-major, leading dimension lda
+ * >= max(rows, 1)), e.g. the R0 that figaro_r0() materialises, by the same
+ * TSQR levels as figaro_r(): partial R's of row tiles, folded level by level,
+ * the last level sign-normalised.  R: device n x n column-major, the strictly
+ * lower part written as 0.  1 <= n <= 128 (FIGARO_EUNSUPPORTED otherwise);
+ * rows may be 0 (R = 0).  The partial R's of the levels live in `workspace`
+ * (device, caller-owned, at least figaro_tsqr_workspace_bytes(rows, n)
+ * bytes, at most 8 MiB for any size; FIGARO_EINVAL if smaller), which the
+ * call may overwrite; it must not be used by another call in flight.
+ * Enqueued on `stream`; no allocation, no host synchronisation.
+ */
+int64_t figaro_tsqr_workspace_bytes(int64_t rows, int32_t n);   /* -1 for an unsupported n */
+figaro_status figaro_tsqr(int64_t rows, int32_t n, const double *A, int64_t lda, double *R,
+                          void *workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/*
  * Per-kernel timing for benchmarks.  While enabled, the compute calls record a
  * pair of HIP events on the caller's stream around every kernel launch, in a
  * pool of `capacity` pairs (events are created here, not in the compute

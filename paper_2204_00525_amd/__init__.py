@@ -99,6 +99,8 @@ def lib():
                                            ctypes.POINTER(PlanOptions), i32, vp]),
         "figaro_plan_tuning": (i32, [vp, ctypes.POINTER(PlanOptions), ctypes.POINTER(dbl)]),
         "figaro_debug_dense_step": (i32, [i32, i64, vp, i64, i32, i64, i32, vp, i64, vp, vp]),
+        "figaro_tsqr_workspace_bytes": (i64, [i64, i32]),
+        "figaro_tsqr": (i32, [i64, i32, vp, i64, vp, vp, i64, vp]),
     }
     optional = {
         "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, pi64, vp]),
@@ -532,6 +534,38 @@ def debug_dense_step(A, workgroups: int, tiles_per_wave: int, variant: int = 0, 
                                          tiles_per_wave, variant, ctypes.c_void_p(out.data_ptr()), workgroups * n,
                                          None, _stream_handle(stream)), None)
     return out.t()
+
+
+def _colmajor(A):
+    """(rows, n) device tensor -> (tensor holding column-major storage,
+    leading dimension): A itself when its rows are contiguous and its columns
+    at least `rows` apart, else a column-major copy."""
+    rows, n = A.shape
+    if A.stride(0) == 1 and (n <= 1 or A.stride(1) >= max(rows, 1)):
+        return A, max(A.stride(1) if n > 1 else rows, 1)
+    return A.t().contiguous(), max(rows, 1)
+
+
+def tsqr_workspace_bytes(rows: int, n: int) -> int:
+    return int(lib().figaro_tsqr_workspace_bytes(rows, n))
+
+
+def tsqr(A, workspace=None, stream=None):
+    """R (n x n, non-negative diagonal) of a device FP64 matrix A (rows x n)
+    by the post-processing TSQR; the partial R's go to `workspace` (a device
+    tensor of at least tsqr_workspace_bytes(rows, n) bytes), allocated here
+    when it is None."""
+    import torch
+    rows, n = A.shape
+    At, lda = _colmajor(A)
+    R = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    if workspace is None:
+        nbytes = tsqr_workspace_bytes(rows, n)
+        workspace = torch.empty((max(nbytes, 8) + 7) // 8, dtype=torch.float64, device=A.device)
+    _check(lib().figaro_tsqr(rows, n, ctypes.c_void_p(At.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()),
+                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                             _stream_handle(stream)), None)
+    return R.t()
 
 
 class Batch:

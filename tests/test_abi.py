@@ -89,3 +89,26 @@ def test_batch_rejects_bad_plans():
     assert b"analyze-only" in L.figaro_last_error(None)
     arr2 = (ctypes.c_void_p * 2)(p._handle.value, None)
     assert L.figaro_batch_create(ctypes.byref(h), 2, arr2, 0) == 1     # NULL plan
+
+
+def test_tsqr_workspace_is_bounded_and_checked():
+    """figaro_tsqr: workspace sizes stay within 8 MiB for any input, and bad
+    arguments are rejected before anything is launched."""
+    L = F.lib()
+    for n in (1, 7, 16, 17, 32, 40, 41, 64, 100, 128):
+        for rows in (0, 1, 100, 10**4, 10**6, 10**8, 10**11):
+            b = L.figaro_tsqr_workspace_bytes(rows, n)
+            assert 0 <= b <= 8 << 20, (n, rows, b)
+        assert L.figaro_tsqr_workspace_bytes(10**6, n) > 0
+    assert L.figaro_tsqr_workspace_bytes(100, 0) == -1
+    assert L.figaro_tsqr_workspace_bytes(100, 129) == -1
+    dummy = ctypes.c_void_p(0x1000)
+    # unsupported width, negative rows, small leading dimension, missing or
+    # short workspace
+    assert L.figaro_tsqr(100, 129, dummy, 100, dummy, dummy, 1 << 30, None) == 9
+    assert L.figaro_tsqr(-1, 8, dummy, 100, dummy, dummy, 1 << 30, None) == 1
+    assert L.figaro_tsqr(100, 8, dummy, 99, dummy, dummy, 1 << 30, None) == 1
+    need = L.figaro_tsqr_workspace_bytes(10**6, 8)
+    assert L.figaro_tsqr(10**6, 8, dummy, 10**6, dummy, None, need, None) == 1
+    assert L.figaro_tsqr(10**6, 8, dummy, 10**6, dummy, dummy, need - 8, None) == 1
+    assert b"workspace" in L.figaro_last_error(None)

@@ -82,3 +82,46 @@ def test_coverage_is_checked(F):
     A = torch.zeros((F.debug_dense_rows(16, 0, 1) + 1, 16), dtype=torch.float64, device="cuda")
     with pytest.raises(F.FigaroError):
         F.debug_dense_step(A, 1, 1, 0)
+
+
+# figaro_tsqr: the whole post-processing QR (every level) of a plain matrix.
+# Sizes: one tile, one workgroup with a ragged tile, several levels, and a
+# first level at its workgroup cap (many tiles per workgroup); column scales
+# 10^U[-3,3] so that every column is compared against its own norm.
+TSQR_CASES = [(1, 1), (1, 5000), (7, 0), (7, 3), (7, 100), (8, 70001), (16, 1024), (16, 200003),
+              (17, 129), (24, 50000), (32, 128), (32, 300001), (40, 90001), (41, 777), (64, 20000),
+              (100, 5000), (128, 40000)]
+
+
+@pytest.mark.parametrize("n,rows", TSQR_CASES)
+def test_tsqr_matches_householder(F, oracle_lib, n, rows):
+    import torch
+    rng = np.random.default_rng(1000 * n + rows % 997)
+    A = rng.standard_normal((rows, n)) * 10.0 ** rng.uniform(-3, 3, n)
+    R = F.tsqr(torch.as_tensor(A).cuda()).cpu().numpy()
+    assert np.all(np.tril(R, -1) == 0.0)
+    assert np.all(np.diag(R) >= 0)
+    if rows < n:     # R is not unique: compare R^T R
+        Ghi, Glo = oracle_lib.gram_ld(np.asfortranarray(A))
+        assert _relf(R.T @ R, Ghi + Glo) <= 1e-13 if rows else np.all(R == 0)
+        return
+    ref, _ = oracle_lib.householder_r(np.asfortranarray(A))
+    err, cerr = _relf(R, ref), colscaled(R, ref)
+    print(f"[tsqr] n={n} rows={rows} rel_err={err:.2e} colscaled={cerr:.2e}", flush=True)
+    assert err <= 1e-10
+    assert cerr <= 1e-10
+
+
+def test_tsqr_leading_dimension_and_workspace(F, oracle_lib):
+    """A submatrix view (leading dimension larger than the rows) and an
+    explicitly passed workspace of exactly the reported size."""
+    import torch
+    rng = np.random.default_rng(5)
+    big = torch.as_tensor(np.asfortranarray(rng.standard_normal((90000, 40)))).cuda()
+    A = big[:80000, 3:30]          # column-major storage, leading dimension 90000
+    nbytes = F.tsqr_workspace_bytes(80000, 27)
+    ws = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    R = F.tsqr(A, workspace=ws).cpu().numpy()
+    ref, _ = oracle_lib.householder_r(np.asfortranarray(A.cpu().numpy()))
+    assert _relf(R, ref) <= 1e-10
+    assert colscaled(R, ref) <= 1e-10
