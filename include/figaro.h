@@ -225,7 +225,7 @@ figaro_status figaro_r0(figaro_plan_t plan, const double *const *values, const i
  * TSQR levels as figaro_r(): partial R's of row tiles, folded level by level,
  * the last level sign-normalised.  R: device n x n column-major, the strictly
  * lower part written as 0.  1 <= n <= 128 (FIGARO_EUNSUPPORTED otherwise);
- * rows may be 0 (R = 0).  The partial R's of the levels live in `workspace`
+ * rows may be 0 (R = 0; A may then be NULL).  The partial R's of the levels live in `workspace`
  * (device, caller-owned, at least figaro_tsqr_workspace_bytes(rows, n)
  * bytes, at most 8 MiB for any size; FIGARO_EINVAL if smaller), which the
  * call may overwrite; it must not be used by another call in flight.
@@ -234,6 +234,22 @@ figaro_status figaro_r0(figaro_plan_t plan, const double *const *values, const i
 int64_t figaro_tsqr_workspace_bytes(int64_t rows, int32_t n);   /* -1 for an unsupported n */
 figaro_status figaro_tsqr(int64_t rows, int32_t n, const double *A, int64_t lda, double *R,
                           void *workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/*
+ * figaro_tsqr() for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same levels and kernels, and the same R bit for bit, with the partial
+ * R's in a static 8 MiB device array of the library instead of a workspace.
+ * Each GPU holds its own copy of the array from the first call on it (its
+ * address is looked up then, with that device current) until the process
+ * ends.  Arguments as for figaro_tsqr(); any row count works (the levels are
+ * shaped to fit the array), n beyond 128 gives FIGARO_EUNSUPPORTED.  Every
+ * call on a GPU uses that GPU's one array: calls that may overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ * Allocates nothing; enqueued on `stream`, no host synchronisation.
+ */
+figaro_status figaro_tsqr_noalloc(int64_t rows, int32_t n, const double *A, int64_t lda, double *R,
+                                  hipStream_t stream);
 
 /*
  * Per-kernel timing for benchmarks.  While enabled, the compute calls record a

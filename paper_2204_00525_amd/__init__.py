@@ -101,6 +101,7 @@ def lib():
         "figaro_debug_dense_step": (i32, [i32, i64, vp, i64, i32, i64, i32, vp, i64, vp, vp]),
         "figaro_tsqr_workspace_bytes": (i64, [i64, i32]),
         "figaro_tsqr": (i32, [i64, i32, vp, i64, vp, vp, i64, vp]),
+        "figaro_tsqr_noalloc": (i32, [i64, i32, vp, i64, vp, vp]),
     }
     optional = {
         "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, pi64, vp]),
@@ -566,6 +567,25 @@ def tsqr(A, workspace=None, stream=None):
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
                              _stream_handle(stream)), None)
     return R.t()
+
+
+def tsqr_noalloc(A, R=None, stream=None):
+    """figaro_tsqr_noalloc(): as tsqr(), with the library's static device
+    array instead of a workspace.  A must already be column-major (rows
+    contiguous), since a copy would allocate; R (n x n, column-major storage)
+    may be passed in to keep the call free of allocations."""
+    import torch
+    rows, n = A.shape
+    if not (A.stride(0) == 1 and (n <= 1 or A.stride(1) >= max(rows, 1))):
+        raise ValueError("tsqr_noalloc needs a column-major A")
+    lda = max(A.stride(1) if n > 1 else rows, 1)
+    if R is None:
+        R = torch.empty((n, n), dtype=torch.float64, device=A.device).t()
+    elif R.shape != (n, n) or R.stride() != (1, n) or R.dtype != torch.float64:
+        raise ValueError("R must be an n x n column-major FP64 tensor")
+    _check(lib().figaro_tsqr_noalloc(rows, n, ctypes.c_void_p(A.data_ptr()), lda, ctypes.c_void_p(R.data_ptr()),
+                                     _stream_handle(stream)), None)
+    return R
 
 
 class Batch:

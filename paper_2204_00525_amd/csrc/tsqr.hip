@@ -5,13 +5,17 @@
 // folds the stacked partial R's of the level before, and the last level (a
 // single workgroup) sign-normalises.
 //
-// The partial R's live in a workspace the caller passes.  The number of
-// workgroups of a level is capped so that two consecutive levels' partial
-// R's take at most kScratchBytes / 2 each; a larger input gives the first
-// level more tiles per workgroup rather than more workgroups.
+// Two entry points share the levels and the kernels: figaro_tsqr() keeps
+// the partial R's in a workspace the caller passes, figaro_tsqr_noalloc() in
+// `scratch`, a static device array of this file (one copy per GPU, held
+// until the process ends).  The number of workgroups of a level is capped
+// so that two consecutive levels' partial R's fit half of that array each;
+// a larger input gives the first level more tiles per workgroup rather than
+// more workgroups, so the row count is not limited by the array.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,6 +32,15 @@ namespace {
 // bound on the partial R's of two consecutive levels together
 constexpr int64_t kScratchBytes = 8ll << 20;
 constexpr int64_t kScratchDoubles = kScratchBytes / 8;
+constexpr int kMaxDevices = 64;
+
+// Device memory of the allocation-free entry point.  In host code this name
+// is a stand-in for the device symbol, not a device address: the address of
+// each GPU's copy comes from hipGetSymbolAddress() and is kept per device.
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
 
 figaro_status fail(figaro_status st, const std::string &msg) {
     g_thread_error = msg;
@@ -35,7 +48,7 @@ figaro_status fail(figaro_status st, const std::string &msg) {
 }
 
 // Workgroups of one level: enough to fill the chip, capped so that the
-// partial R's of two consecutive levels take at most kScratchBytes / 2 each.
+// partial R's of two consecutive levels fit half of the static array each.
 int64_t max_workgroups(int32_t n) {
     return std::max<int64_t>(1, std::min<int64_t>(4096, kScratchDoubles / 2 / ((int64_t)n * n)));
 }
@@ -79,7 +92,9 @@ int64_t workspace_doubles(const Levels &L, int32_t n) { return (L.buf_rows[0] + 
 
 figaro_status check(int64_t rows, int32_t n, const double *A, int64_t lda, const double *R) {
     if (n < 1 || n > kMaxCols) return fail(FIGARO_EUNSUPPORTED, "n must be between 1 and 128");
-    if (rows < 0 || !A || !R || lda < std::max<int64_t>(rows, 1)) return fail(FIGARO_EINVAL, "bad argument");
+    // A may be NULL when it has no rows (nothing is read)
+    if (rows < 0 || (!A && rows > 0) || !R || lda < std::max<int64_t>(rows, 1))
+        return fail(FIGARO_EINVAL, "bad argument");
     return FIGARO_OK;
 }
 
@@ -129,6 +144,33 @@ figaro_status figaro_tsqr(int64_t rows, int32_t n, const double *A, int64_t lda,
         return fail(FIGARO_EINVAL, "workspace smaller than figaro_tsqr_workspace_bytes()");
     double *w = static_cast<double *>(workspace);
     return run_levels(L, n, A, lda, R, w, w ? w + L.buf_rows[0] * n : nullptr, stream);
+}
+
+figaro_status figaro_tsqr_noalloc(int64_t rows, int32_t n, const double *A, int64_t lda, double *R,
+                                  hipStream_t stream) {
+    figaro_status st = check(rows, n, A, lda, R);
+    if (st != FIGARO_OK) return st;
+    const Levels L = plan_levels(rows, n);
+    if (workspace_doubles(L, n) > kScratchDoubles)   // excluded by the workgroup cap
+        return fail(FIGARO_EUNSUPPORTED, "partial R factors exceed the 8 MiB static scratch array");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(FIGARO_EHIP, "hipGetDevice failed");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FIGARO_EUNSUPPORTED, "device index beyond 63");
+    double *base = nullptr;
+    {
+        // first call on this device (the current one): the address of its
+        // copy of the array
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(FIGARO_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            g_scratch_ptr[dev] = static_cast<double *>(ptr);
+        }
+        base = g_scratch_ptr[dev];
+    }
+    return run_levels(L, n, A, lda, R, base, base + L.buf_rows[0] * n, stream);
 }
 
 }  // extern "C"
