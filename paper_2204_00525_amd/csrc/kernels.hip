@@ -249,6 +249,140 @@ __device__ __forceinline__ void qr_step(double (&x)[RPL][NB], double *rw, int nc
     else qr_accumulate_rot<NB, RPL>(x, rw, ncols);
 }
 
+// Blocked step for tiles of 32 columns (compact WY form): the first 16
+// columns of [R; X] are factored column by column as above, keeping the tile
+// part y_J = scale * X_J of every Householder vector v_J = [e_J; y_J] in
+// place of the eliminated column; the 16 reflectors then reach the trailing
+// 16 columns at once, and the last 16 columns are factored column by column.
+// With Y the 16 vectors' tile parts, X the trailing tile columns and R' the
+// trailing part of R's first 16 rows, the products G = Y^T Y and W = Y^T X
+// are sums over the tile's rows, which the matrix cores form with
+// v_mfma_f64_16x16x4f64 instead of one cross-lane reduction per entry.
+// Applying H_0, ..., H_15 in turn then needs, for the reflector J,
+//   z_J = R'_J + W_J - sum_{i<J} G_Ji zh_i,   zh_J = tau_J z_J,
+// (v_J^T of the trailing columns after H_0..H_{J-1}; v_i^T v_J = G_iJ for
+// i != J), after which R'_J -= zh_J and X -= Y Zh.  This is the forward
+// compact WY update Q^T C = C - V T^T V^T C with the triangular factor T
+// applied by substitution.
+//
+// Operand layouts of v_mfma_f64_16x16x4f64 (D = A B + C; lane l, register r):
+// A[l % 16][l / 16], B[l / 16][l % 16], D[4 r + l / 16][l % 16].  Both
+// products take A[m][k] = Y[row k][m]; B[k][n] = Y[row k][n] or X[row k][n],
+// so a lane needs column l % 16 of rows that depend on l / 16 only.  The
+// tile's rows are moved there through the wave's LDS area, 64 rows (one per
+// lane) at a time: row k of lane L's registers is written as row L of a
+// column-major 64-row block, and lane (g, c) reads rows 16 g .. 16 g + 15 of
+// column c (the sums run over all rows, so any row order will do).
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+constexpr int kPanelCols = 16;
+constexpr int kWyLd = 66;                                  // padded column stride of the 64-row block
+constexpr int kWyScratch = 2 * kPanelCols * kWyLd + kPanelCols;   // block (reused for G, W, Zh) + tau
+
+template <int RPL, int J>
+__device__ __forceinline__ void wy_panel_column(double (&x)[RPL][32], double *rw, double *tau, int lane) {
+    constexpr int NB = 32, C = kPanelCols - J;
+    double d[C], p[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc = fma(x[r][J], x[r][J + k], acc);
+        d[k] = acc;
+        p[k] = rw[J * NB + J + k];
+    }
+    wave_sum_batch<C>(d);
+    const Reflector h = reflector(p[0], d[0]);
+#pragma unroll
+    for (int k = 1; k < C; ++k) {
+        const double w = fma(h.scale, d[k], p[k]);
+        const double g = h.ts * w;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) x[r][J + k] = fma(-g, x[r][J], x[r][J + k]);
+        rw[J * NB + J + k] = fma(-h.tau, w, p[k]);
+    }
+    rw[J * NB + J] = h.rjj;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) x[r][J] *= h.scale;
+    if (lane == 0) tau[J] = h.tau;
+}
+
+template <int RPL, int... Js>
+__device__ __forceinline__ void wy_panel(double (&x)[RPL][32], double *rw, double *tau, int lane,
+                                         std::integer_sequence<int, Js...>) {
+    (wy_panel_column<RPL, Js>(x, rw, tau, lane), ...);
+}
+
+template <int RPL, int... Js>
+__device__ __forceinline__ void wy_tail_columns(double (&x)[RPL][32], double *rw, std::integer_sequence<int, Js...>) {
+    (qr_column<32, RPL, kPanelCols + Js>(x, rw), ...);
+}
+
+template <int RPL>
+__device__ __forceinline__ void qr_step_wy32(double (&x)[RPL][32], double *rw, double *sc, int lane) {
+    constexpr int NB = 32, P = kPanelCols, LD = kWyLd;
+    double *tb = sc;                       // [32][LD]: the 64-row block
+    double *tau = sc + 2 * P * LD;         // [16]
+    wy_panel<RPL>(x, rw, tau, lane, std::make_integer_sequence<int, P>{});
+    // G = Y^T Y and W = Y^T X on the matrix cores
+    const int g = lane >> 4, c = lane & 15;
+    mfma_f64x4 accG = {0.0, 0.0, 0.0, 0.0}, accW = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < RPL; ++k) {
+#pragma unroll
+        for (int col = 0; col < NB; ++col) tb[col * LD + lane] = x[k][col];
+#pragma unroll
+        for (int q = 0; q < 16; q += 2) {
+            const double2 y2 = *reinterpret_cast<const double2 *>(tb + c * LD + 16 * g + q);
+            const double2 x2 = *reinterpret_cast<const double2 *>(tb + (P + c) * LD + 16 * g + q);
+            accG = __builtin_amdgcn_mfma_f64_16x16x4f64(y2.x, y2.x, accG, 0, 0, 0);
+            accW = __builtin_amdgcn_mfma_f64_16x16x4f64(y2.x, x2.x, accW, 0, 0, 0);
+            accG = __builtin_amdgcn_mfma_f64_16x16x4f64(y2.y, y2.y, accG, 0, 0, 0);
+            accW = __builtin_amdgcn_mfma_f64_16x16x4f64(y2.y, x2.y, accW, 0, 0, 0);
+        }
+    }
+    // G and W row-major [16][16] (over the block, whose reads are done)
+    double *G = tb, *W = tb + P * P, *Zh = tb + 2 * P * P;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        G[(4 * r + g) * P + c] = accG[r];
+        W[(4 * r + g) * P + c] = accW[r];
+    }
+    // the reflectors in turn on column c of the trailing block (the four
+    // lanes of a column compute the same values; one of them stores)
+    double zh[P];
+#pragma unroll
+    for (int J = 0; J < P; ++J) {
+        const double rjc = rw[J * NB + P + c];
+        double z = rjc + W[J * P + c];
+#pragma unroll
+        for (int i = 0; i < J; ++i) z = fma(-G[J * P + i], zh[i], z);
+        zh[J] = tau[J] * z;
+        if (lane < P) {
+            rw[J * NB + P + c] = rjc - zh[J];
+            Zh[J * P + c] = zh[J];
+        }
+    }
+    // X -= Y Zh on the tile's rows
+#pragma unroll
+    for (int J = 0; J < P; ++J) {
+#pragma unroll
+        for (int n = 0; n < P; ++n) {
+            const double zv = Zh[J * P + n];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) x[r][P + n] = fma(-x[r][J], zv, x[r][P + n]);
+        }
+    }
+    wy_tail_columns<RPL>(x, rw, std::make_integer_sequence<int, NB - P>{});
+}
+
+// Whether the head/tail kernel of this shape uses the blocked step (32
+// columns, fully unrolled, one wave per SIMD: the LDS then holds the 64-row
+// blocks of all four waves).
+template <int NB, bool ROT, int OCC>
+constexpr bool use_wy() {
+    return NB == 32 && !ROT && OCC == 1;
+}
+
 // Each wave keeps its running R in its own LDS slice (NB x NB doubles,
 // row-major, zero below the diagonal; the compact form adds a spare row).
 // Merging the waves of a workgroup: after a barrier, wave 0 folds the R
@@ -331,6 +465,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     __shared__ double lds[FUSE ? kWavesPerBlock * r_slice_doubles<NB, ROT>() : 1];
     __shared__ double stage_lds[STAGE ? kWavesPerBlock * S::doubles : 1];
     __shared__ int32_t prefetch_sink[JOIN ? 64 : 1];
+    constexpr bool WY = FUSE && use_wy<NB, ROT, OCC>();
+    __shared__ double wy_lds[WY ? kWavesPerBlock * kWyScratch : 1];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int wave = blockIdx.x * kWavesPerBlock + wib;
@@ -436,7 +572,11 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                 continue;
             }
         }
-        if constexpr (FUSE) qr_step<NB, RPL, ROT>(x, rw, a.ncols);
+        if constexpr (WY) {
+            if constexpr (NB == 32) qr_step_wy32<RPL>(x, rw, wy_lds + wib * kWyScratch, lane);
+        } else if constexpr (FUSE) {
+            qr_step<NB, RPL, ROT>(x, rw, a.ncols);
+        }
     }
     if constexpr (FUSE) {
         if (wib > 0) __syncthreads();
