@@ -636,8 +636,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 }
 
 // Cooperative dense TSQR step (n > 16): the W waves of a workgroup share
-// each tile of kCoopRows rows; wave w holds columns [CW w, CW w + CW) of the
-// tile (kCoopRPL rows per lane) and the same columns of the workgroup's R
+// each tile of 64 coop_rpl(CW) rows; wave w holds columns [CW w, CW w + CW)
+// of the tile (coop_rpl(CW) rows per lane) and the same columns of the workgroup's R
 // (all n rows, row-major, in its LDS slice).  CW is 4 for n <= 32 (W = 6 or
 // 8), 8 for n <= 40 (W = 5) and 32 for wider matrices.  At the step of column j the wave
 // that owns j forms the reflector from its own column (for CW = 32 kept at
@@ -652,17 +652,43 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 // step takes the latency of one column's reflector per column instead of
 // that of all its reductions.  Every wave runs the same number of steps and
 // barriers.  Workgroup b folds rows [b W', (b+1) W'), W' = tiles_per_wave *
-// kCoopRows, into one R; the single workgroup of the last level
+// 64 coop_rpl(CW) rows, into one R; the single workgroup of the last level
 // sign-normalises it.
 constexpr int kWideCols = 32;
 constexpr int kNarrowCols = 8;
-constexpr int kCoopRPL = 2;
-constexpr int kCoopRows = 64 * kCoopRPL;
+// rows per lane of a shared tile: narrow column blocks (at most 8 columns
+// per wave) hold 8 rows of each column per lane (512-row tiles, so a level
+// divides the rows by 16 at n = 32); wide blocks (32 columns per wave) 2
+constexpr int coop_rpl(int cw) { return cw <= kNarrowCols ? 8 : 2; }
 
 // One column step of the shared-tile kernel with the column's place in its
 // block (JL) known at compile time (narrow blocks): the owner reduces only
 // the JL..CW-1 columns it still holds and reads its registers in place, with
 // no rotation.  j = o CW + JL >= n is skipped by every wave alike.
+// Dot products over a lane's rows of a shared tile, in two interleaved
+// partial sums (even and odd rows) to halve the dependent chain.
+template <int RPL, int CW>
+__device__ __forceinline__ double dot_rows(const double (&x)[RPL][CW], int a, int b) {
+    double e = 0.0, o = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; r += 2) {
+        e = fma(x[r][a], x[r][b], e);
+        if (r + 1 < RPL) o = fma(x[r + 1][a], x[r + 1][b], o);
+    }
+    return e + o;
+}
+
+template <int RPL, int CW>
+__device__ __forceinline__ double dot_rows(const double (&v)[RPL], const double (&x)[RPL][CW], int b) {
+    double e = 0.0, o = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; r += 2) {
+        e = fma(v[r], x[r][b], e);
+        if (r + 1 < RPL) o = fma(v[r + 1], x[r + 1][b], o);
+    }
+    return e + o;
+}
+
 template <int W, int CW, int RPL, int JL>
 __device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, double (*xb)[64 * RPL],
                                             double (*sc)[4], int wib, int o, int n, int lane, int par) {
@@ -676,10 +702,7 @@ __device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, do
         double d[C], p[C];
 #pragma unroll
         for (int k = 0; k < C; ++k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) acc = fma(x[r][JL], x[r][JL + k], acc);
-            d[k] = acc;
+            d[k] = dot_rows<RPL>(x, JL, JL + k);
             p[k] = rw[j * CW + JL + k];
         }
         wave_sum_batch<C>(d);
@@ -707,10 +730,7 @@ __device__ __forceinline__ void coop_column(double (&x)[RPL][CW], double *rw, do
         const double scale = sc[slot][0], ts = sc[slot][1], tau = sc[slot][2];
 #pragma unroll
         for (int k = 0; k < CW; ++k) {
-            double acc = 0.0;
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) acc = fma(xj[r], x[r][k], acc);
-            d[k] = acc;
+            d[k] = dot_rows<RPL>(xj, x, k);
             p[k] = rw[j * CW + k];
         }
         wave_sum_batch<CW>(d);
@@ -734,7 +754,7 @@ __device__ __forceinline__ void coop_block(double (&x)[RPL][CW], double *rw, dou
 
 template <int W, int CW>
 __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
-    constexpr int RPL = kCoopRPL, T = kCoopRows;
+    constexpr int RPL = coop_rpl(CW), T = 64 * RPL;
     constexpr int NW = CW * W;                   // rows of an R slice
     constexpr int SL = (NW + 1) * CW;            // slice: NW rows + a spare row
     __shared__ double rsl[W * SL];
@@ -999,7 +1019,8 @@ int tile_items_for(int ncols, int variant) {
 bool dense_coop(int ncols) { return ncols > 16; }
 
 int dense_tile_rows_for(int ncols, int variant) {
-    return dense_coop(ncols) ? kCoopRows : tile_items_for(ncols, variant);
+    if (!dense_coop(ncols)) return tile_items_for(ncols, variant);
+    return 64 * coop_rpl(ncols <= kFusedMaxCols ? kNarrowCols : kWideCols);
 }
 
 int dense_waves_per_block(int ncols) {
