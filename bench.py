@@ -160,8 +160,37 @@ def comparator(F, div: int):
             "reference": "CPU oracle (materialised join, textbook Householder)"}
 
 
-def star(F, steps, warmup, with_comparator):
-    """Key/foreign-key star join: forward, forward+backward, comparator."""
+def tree_choice(F, inst, R, t_fwd, steps, warmup):
+    """Join-tree selection on the star join: the tree the chooser picks
+    (host, from the keys) against the tree rooted at the fact table, whose
+    join would be carried whole into the post-processing QR; both forward
+    passes timed, R compared."""
+    import torch
+    import synth
+    t0 = time.perf_counter()
+    parents, cost = F.choose_join_tree(inst)
+    t_choose = time.perf_counter() - t0
+    fact = [i for i, rel in enumerate(inst.rels) if rel.name == "F"][0]
+    fact_rooted = [fact if i != fact else -1 for i in range(inst.r)]
+    bad = synth.Instance(inst.name, [synth.Rel(rel.key_attrs, rel.keys, rel.values, p, rel.name)
+                                     for rel, p in zip(inst.rels, fact_rooted)], inst.meta)
+    plan_b = F.plan_from_instance(bad)
+    vals_b = F.device_values(plan_b, bad)
+    t_bad, R_b, _ = time_forward(plan_b, vals_b, max(3, steps // 2), warmup)
+    diff = float(torch.linalg.norm(R_b - R) / torch.linalg.norm(R))
+    plan_b.close()
+    del vals_b
+    torch.cuda.empty_cache()
+    return {"chosen_parents": parents, "chosen_score": cost, "choose_s": t_choose,
+            "given_tree_is_chosen": parents == [rel.parent for rel in inst.rels],
+            "fact_rooted_score": F.join_tree_cost(inst, fact_rooted),
+            "chosen_fwd_ms": t_fwd * 1e3, "fact_rooted_fwd_ms": t_bad * 1e3,
+            "speedup_chosen_over_fact_rooted": t_bad / t_fwd, "rel_diff_R": diff}
+
+
+def star(F, steps, warmup, with_comparator, with_tree_choice=True):
+    """Key/foreign-key star join: forward, forward+backward, comparator, join
+    tree choice."""
     import torch
     import oracle
     import synth
@@ -180,6 +209,8 @@ def star(F, steps, warmup, with_comparator):
            "tuples": inst.M, "join_rows": plan.join_rows, "plan_s": t_plan,
            "fwd_ms": t_fwd * 1e3, "fwd_tuples_per_s": inst.M / t_fwd,
            "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_tuples_per_s": inst.M / t_fb}
+    if with_tree_choice:
+        out["tree_choice"] = tree_choice(F, inst, R, t_fwd, steps, warmup)
     if with_comparator:
         log("star join: materialising 10^7 x 40 for the comparator")
         t0 = time.perf_counter()
@@ -284,6 +315,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-star", action="store_true")
+    ap.add_argument("--no-tree-choice", action="store_true")
     ap.add_argument("--batched", type=int, default=48,
                     help="instances of the batched workload (the first N of 512; 0: skip)")
     ap.add_argument("--cpu-div", type=int, default=100)
@@ -375,7 +407,7 @@ def main():
     del vals
     torch.cuda.empty_cache()
     if not args.no_star:
-        out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator)
+        out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator, not args.no_tree_choice)
     if args.batched > 0:
         out["batched"] = batched(F, args.batched, max(3, args.steps // 2), 2)
     if not args.no_comparator:

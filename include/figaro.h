@@ -322,6 +322,39 @@ figaro_status figaro_batch_capture(figaro_batch_t batch, const double *const *co
 figaro_status figaro_batch_launch(figaro_batch_t batch, hipStream_t stream);
 
 /*
+ * Join-tree selection (experiments section, "Effect of join trees": the
+ * method runs fastest on the join tree with the smallest intermediate
+ * results, which keeps a large fact table away from the root so that its
+ * join attributes are aggregated away early).  A join tree here is a
+ * spanning tree over the relations in which the relations holding any one
+ * attribute stay connected (running intersection) and every key attribute is
+ * shared with a neighbour; any relation may be the root.  The score of a
+ * rooted tree is the work of the QR of R0, rows x columns^2 summed over its
+ * blocks:
+ *   sum_i (m_i - G_i) n_i^2 + sum_{i not root} (G_i - P_i) nsub_i^2 + G_root n^2
+ * with m_i the rows, n_i the columns and G_i the distinct values of the join
+ * attributes of relation i, P_i the distinct values of those it shares with
+ * its parent, nsub_i the columns of its subtree, n the total (dangling
+ * tuples are not removed first: for a database that is not fully reduced the
+ * score is an estimate).  Keys as in figaro_relation_desc (host arrays when
+ * keys_on_host is 1, else device arrays read on `stream`, which is then
+ * synchronised); r <= 12.
+ *
+ * figaro_join_tree_cost(): the score of the tree given by rels[i].parent
+ * (FIGARO_ENOTTREE if it is not a join tree).
+ * figaro_choose_join_tree(): the lowest-scoring join tree over every join
+ * tree and root (rels[i].parent is ignored); parents_out[i] receives the
+ * parent of relation i (-1 for the root), *cost_out (may be NULL) its score.
+ * Relations that share no attributes are linked by Cartesian products only
+ * when the shared attributes alone leave them disconnected.
+ * FIGARO_ENOTTREE if no join tree exists (a cyclic join).  Host only.
+ */
+figaro_status figaro_join_tree_cost(int32_t r, const figaro_relation_desc *rels, int32_t keys_on_host,
+                                    double *cost_out, hipStream_t stream);
+figaro_status figaro_choose_join_tree(int32_t r, const figaro_relation_desc *rels, int32_t keys_on_host,
+                                      int32_t *parents_out, double *cost_out, hipStream_t stream);
+
+/*
  * Autotuner: builds the plan under each option set of `candidates`
  * (ncandidates <= 0 or NULL: register-tile variants 0 and 2 times wave caps
  * 512, 1024, 2048; analyze_only is ignored), times `reps` forward passes of

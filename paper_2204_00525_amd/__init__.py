@@ -102,6 +102,9 @@ def lib():
         "figaro_tsqr_workspace_bytes": (i64, [i64, i32]),
         "figaro_tsqr": (i32, [i64, i32, vp, i64, vp, vp, i64, vp]),
         "figaro_tsqr_noalloc": (i32, [i64, i32, vp, i64, vp, vp]),
+        "figaro_join_tree_cost": (i32, [i32, ctypes.POINTER(RelationDesc), i32, ctypes.POINTER(dbl), vp]),
+        "figaro_choose_join_tree": (i32, [i32, ctypes.POINTER(RelationDesc), i32, ctypes.POINTER(i32),
+                                          ctypes.POINTER(dbl), vp]),
     }
     optional = {
         "figaro_r_backward": (i32, [vp, pp, pi64, vp, vp, pp, pi64, vp]),
@@ -505,6 +508,43 @@ def device_values(plan: Plan, inst, device="cuda") -> List:
         v = torch.as_tensor(np.ascontiguousarray(rel.values, dtype=np.float64)).to(device)
         out.append(plan.to_plan_order(i, v))
     return out
+
+
+def _host_descs(inst, parents=None):
+    """Relation descriptors with host int64 keys for the join-tree calls."""
+    keep = []
+    arr = (RelationDesc * inst.r)()
+    for i, rel in enumerate(inst.rels):
+        attrs = np.ascontiguousarray(rel.key_attrs, dtype=np.int32)
+        keys = np.ascontiguousarray(rel.keys, dtype=np.int64).reshape(len(rel.key_attrs), rel.rows)
+        keep += [attrs, keys]
+        arr[i].rows = rel.rows
+        arr[i].num_keys = len(rel.key_attrs)
+        arr[i].key_attr = attrs.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        arr[i].key_cols = ctypes.c_void_p(keys.ctypes.data)
+        arr[i].key_dtype = 8
+        arr[i].num_cols = rel.ncols
+        arr[i].parent = rel.parent if parents is None else int(parents[i])
+    return arr, keep
+
+
+def join_tree_cost(inst, parents=None) -> float:
+    """Score (QR work: rows x columns^2 over the blocks of R0) of the join
+    tree given by the instance's parents (or `parents`)."""
+    arr, keep = _host_descs(inst, parents)
+    c = ctypes.c_double()
+    _check(lib().figaro_join_tree_cost(inst.r, arr, 1, ctypes.byref(c), None), None)
+    return c.value
+
+
+def choose_join_tree(inst):
+    """The join tree (parent of every relation, -1 for the root) with the
+    lowest score over all join trees and roots, and that score."""
+    arr, keep = _host_descs(inst)
+    parents = (ctypes.c_int32 * inst.r)()
+    c = ctypes.c_double()
+    _check(lib().figaro_choose_join_tree(inst.r, arr, 1, parents, ctypes.byref(c), None), None)
+    return [int(x) for x in parents], c.value
 
 
 def debug_tile_rows(n: int, variant: int = 0) -> int:

@@ -325,3 +325,17 @@ def test_forward_variants(F, oracle_lib, name, tile, variant):
     inst = CASES[name]()
     R, plan, _ = gpu_r(F, inst, variant=variant, tile_items=tile)
     check_r(R, inst, oracle_lib, label=f"[forward-variant] case={name} tile={tile} variant={variant}")
+
+
+def test_join_tree_choice_leaves_r_unchanged(F, oracle_lib):
+    """R does not depend on the join tree (Theorem 6 holds for any of them):
+    the star join at 1/1000 scale with the tree the chooser picks and with
+    the tree rooted at the fact table both match the oracle."""
+    inst = synth.config3(div=1000)
+    parents, _ = F.choose_join_tree(inst)
+    fact = [i for i, rel in enumerate(inst.rels) if rel.name == "F"][0]
+    for par in (parents, [fact if i != fact else -1 for i in range(inst.r)]):
+        re = synth.Instance(inst.name, [synth.Rel(rel.key_attrs, rel.keys, rel.values, p, rel.name)
+                                        for rel, p in zip(inst.rels, par)], inst.meta)
+        R, plan, _ = gpu_r(F, re)
+        check_r(R, inst, oracle_lib, label=f"[tree] parents={par}")
