@@ -188,6 +188,24 @@ def tree_choice(F, inst, R, t_fwd, steps, warmup):
             "speedup_chosen_over_fact_rooted": t_bad / t_fwd, "rel_diff_R": diff}
 
 
+def plan_times(F, inst):
+    """The plan built on the device from device keys (timed, keys uploaded
+    beforehand) and, for comparison, the same plan built on the host from the
+    same device keys."""
+    import torch
+    views = F.instance_views(inst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = F.Plan(views)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    F.Plan(views, host_plan=True).close()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t0
+    return plan, t_dev, t_host
+
+
 def star(F, steps, warmup, with_comparator, with_tree_choice=True):
     """Key/foreign-key star join: forward, forward+backward, comparator, join
     tree choice."""
@@ -196,17 +214,14 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
     import synth
     log("star join: generating inputs")
     inst = synth.config3()
-    t0 = time.perf_counter()
-    plan = F.plan_from_instance(inst)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
+    plan, t_plan, t_plan_host = plan_times(F, inst)
     vals = F.device_values(plan, inst)
     log(f"star join: plan {t_plan:.1f} s")
     t_fwd, R, _ = time_forward(plan, vals, steps, warmup)
     t_fb = time_steps(lambda: fwd_bwd_step(plan, vals), steps, warmup)
     out = {"workload": "star join: fact 10^7 rows x 8 cols with 4 uniform foreign keys into four "
                        "10^5-row dimensions x 8 cols; column scales 10^U[-3,3]; n = 40",
-           "tuples": inst.M, "join_rows": plan.join_rows, "plan_s": t_plan,
+           "tuples": inst.M, "join_rows": plan.join_rows, "plan_s": t_plan, "plan_s_host_builder": t_plan_host,
            "fwd_ms": t_fwd * 1e3, "fwd_tuples_per_s": inst.M / t_fwd,
            "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_tuples_per_s": inst.M / t_fb}
     if with_tree_choice:
@@ -336,10 +351,7 @@ def main():
     torch.cuda.set_device(0)
     log("generating the two-relation inputs")
     inst = synth.config2()
-    t0 = time.perf_counter()
-    plan = F.plan_from_instance(inst)
-    torch.cuda.synchronize()
-    t_plan = time.perf_counter() - t0
+    plan, t_plan, t_plan_host = plan_times(F, inst)
     vals = F.device_values(plan, inst)
     torch.cuda.synchronize()
     log(f"plan built in {t_plan:.2f} s; join rows {plan.join_rows:.0f}")
@@ -398,7 +410,8 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded)",
            "config": {"workload": "two-relation join, 2 x 2,000,000 tuples, 1000 Zipf(1.1) keys, "
                                   "16 + 16 FP64 columns (n = 32)",
-                      "tuples": M, "join_rows": plan.join_rows, "n": plan.n, "plan_s": t_plan},
+                      "tuples": M, "join_rows": plan.join_rows, "n": plan.n, "plan_s": t_plan,
+                      "plan_s_host_builder": t_plan_host},
            "fwd_bwd": {"ms_per_step": t_fb * 1e3, "tuples_per_s": M / t_fb,
                        "loss": "R_nn^2/2 + sum log R_ii"},
            "join_rows_per_s": plan.join_rows / t_step,

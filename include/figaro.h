@@ -111,6 +111,11 @@ typedef struct {
                                    (default): a non-root relation with at most
                                    four children has its first project-away
                                    level read them in place instead */
+    int32_t host_plan;          /* 1: build the plan on the host even when
+                                   the keys are on the device (the keys are
+                                   copied over); 0 (default): device keys are
+                                   sorted, segmented and counted on the
+                                   device.  Both give the same plan. */
 } figaro_plan_options;
 
 /* Count-query selectors for figaro_plan_counts(). */
@@ -128,8 +133,11 @@ typedef enum {
  * reduce dangling tuples, sort each relation on (attributes shared with the
  * parent, then its other key attributes, then row index), segment it into key
  * groups, evaluate the count queries exactly in 64-bit integers, derive the
- * scale factors, and allocate the workspace.  Reads key_cols on `stream`,
- * synchronises it, and copies small tables to the device.
+ * scale factors, and allocate the workspace.  With device keys (the default)
+ * the dictionary encoding, the reduction, the radix sort, the segments, the
+ * child indices, the counts and the first level of every head/tail task are
+ * computed on the device, on `stream`, which the call synchronises a few
+ * times; host keys (or host_plan) run the same steps on the host.
  */
 figaro_status figaro_plan_create(figaro_plan_t *out, int32_t r,
                                  const figaro_relation_desc *rels,

@@ -39,7 +39,8 @@ class RelationDesc(ctypes.Structure):
 class PlanOptions(ctypes.Structure):
     _fields_ = [("tile_items", ctypes.c_int32), ("waves_per_task", ctypes.c_int32),
                 ("keys_on_host", ctypes.c_int32), ("variant", ctypes.c_int32),
-                ("analyze_only", ctypes.c_int32), ("separate_join", ctypes.c_int32)]
+                ("analyze_only", ctypes.c_int32), ("separate_join", ctypes.c_int32),
+                ("host_plan", ctypes.c_int32)]
 
 
 _lib = None
@@ -174,7 +175,7 @@ class Plan:
 
     def __init__(self, relations: Sequence, *, tile_items: int = 0, waves_per_task: int = 0,
                  stream=None, analyze_only: bool = False, variant: int = 0, separate_join: bool = False,
-                 _handle=None):
+                 host_plan: bool = False, _handle=None):
         L = lib()
         if analyze_only:
             self._init_host(relations, tile_items, waves_per_task)
@@ -184,7 +185,8 @@ class Plan:
         else:
             self._handle = ctypes.c_void_p()
             descs, keep = _device_descs(relations)
-            opts = PlanOptions(tile_items, waves_per_task, 0, variant, 0, int(bool(separate_join)))
+            opts = PlanOptions(tile_items, waves_per_task, 0, variant, 0, int(bool(separate_join)),
+                               int(bool(host_plan)))
             st = L.figaro_plan_create(ctypes.byref(self._handle), len(relations), descs, ctypes.byref(opts),
                                       _stream_handle(stream))
             del keep

@@ -332,6 +332,12 @@ struct RelPlan {
     double *d_inv_sqrt_c = nullptr;
     int64_t root_row0 = 0;
     int64_t r0_root_row0 = 0;
+    // plans built on the device: segment offsets and counts stay there, and
+    // the host copies above are fetched when a query asks for them
+    int64_t *d_seg_off = nullptr, *d_par_off = nullptr;   // [G+1], [P+1]
+    int64_t *d_theta = nullptr, *d_phi_circ = nullptr;     // [G]
+    int64_t *d_phi_up = nullptr, *d_phi_down = nullptr;   // [P]
+    bool host_arrays = true;         // perm, seg_off, par_off and the counts are on the host
 };
 
 constexpr int kProfClasses = 8;
@@ -362,6 +368,7 @@ struct figaro_plan_s {
     int32_t waves_cap = 0;
     bool analyze_only = false;
     bool separate_join = false;
+    bool device_plan = false;        // keys segmented and counted on the device
     int32_t variant = 0;
     // stack for the post-processing TSQR
     int64_t stack_rows = 0;
@@ -387,3 +394,47 @@ struct figaro_plan_s {
     double prof_bytes[figaro::kProfClasses] = {0};
     double prof_flops[figaro::kProfClasses] = {0};
 };
+
+namespace figaro {
+
+// Device allocations owned by a plan (freed by figaro_plan_destroy).
+template <typename T>
+inline hipError_t dev_upload(figaro_plan_s *p, T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    size_t bytes = sizeof(T) * std::max<size_t>(src.size(), 1);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    p->allocations.push_back(*dst);
+    p->workspace_bytes += (int64_t)bytes;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return e;
+}
+
+inline hipError_t dev_alloc(figaro_plan_s *p, void **dst, size_t bytes) {
+    *dst = nullptr;
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) return e;
+    p->allocations.push_back(*dst);
+    p->workspace_bytes += (int64_t)std::max<size_t>(bytes, 8);
+    return e;
+}
+
+
+figaro_status set_error(figaro_plan_s *p, figaro_status st, const std::string &msg);
+
+// Levels of a segmented head/tail task from level `first` on (plan.cpp):
+// items grouped by group_off (ngroups + 1 offsets), per-item counts (empty:
+// every item counts 1), per-group tail scale, the chunk size of level 0.
+figaro_status build_task_levels(figaro_plan_s *p, Task &T, int first, int64_t items, std::vector<int64_t> goff,
+                                std::vector<int64_t> cnt, bool unit, const std::vector<double> &phi, int tile);
+figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total);
+// Stack and R0 layout, dense TSQR levels and the remaining workspace, once
+// every task is built (plan.cpp).
+figaro_status finish_plan(figaro_plan_s *p);
+// Key segmentation, count queries and the tasks' first levels on the device
+// (dplan.hip), from the validated tree and columns of p.
+figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc *rels, hipStream_t stream);
+// Host copies of the device plan's arrays for the query calls.
+figaro_status fetch_host_arrays(figaro_plan_s *p, int32_t rel);
+
+}  // namespace figaro

@@ -49,27 +49,6 @@ struct Packer {
     int bits = 0;
 };
 
-template <typename T>
-hipError_t dev_upload(figaro_plan_s *p, T **dst, const std::vector<T> &src) {
-    *dst = nullptr;
-    size_t bytes = sizeof(T) * std::max<size_t>(src.size(), 1);
-    hipError_t e = hipMalloc((void **)dst, bytes);
-    if (e != hipSuccess) return e;
-    p->allocations.push_back(*dst);
-    p->workspace_bytes += (int64_t)bytes;
-    if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
-    return e;
-}
-
-hipError_t dev_alloc(figaro_plan_s *p, void **dst, size_t bytes) {
-    *dst = nullptr;
-    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
-    if (e != hipSuccess) return e;
-    p->allocations.push_back(*dst);
-    p->workspace_bytes += (int64_t)std::max<size_t>(bytes, 8);
-    return e;
-}
-
 struct Builder {
     figaro_plan_s *p;
     int32_t r;
@@ -177,25 +156,24 @@ void postorder(const figaro_plan_s *p, int v, std::vector<int32_t> &out) {
     out.push_back(v);
 }
 
-// Build the levels of one segmented head/tail task.
-//   group_off: [ngroups+1] item offsets of the groups (level 0)
-//   counts   : per-item counts (empty = every item counts 1, unit level 0)
-//   phi      : per-group tail scale
-//   tile     : items per chunk of the first level (the task's tile shape)
+}  // namespace
+
+// Build the levels `first`, first + 1, ... of one segmented head/tail task
+// from the state of level `first`:
+//   goff : [ngroups+1] item offsets of the groups over this level's items
+//   cnt  : per-item counts (empty with unit = every item counts 1, level 0)
+//   phi  : per-group tail scale
+//   tile : items per chunk of the first level (the task's tile shape)
 // The upper levels are small and latency-bound: they take the shape with two
 // waves per SIMD (variant 2) and its smaller chunks, which doubles the waves
 // in flight (ncols <= 32; wider tasks keep the task's shape).
-figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::vector<int64_t> &group_off,
-                         const std::vector<int64_t> &counts, const std::vector<double> &phi, int tile) {
+figaro_status build_task_levels(figaro_plan_s *p, Task &T, int first, int64_t items, std::vector<int64_t> goff,
+                                std::vector<int64_t> cnt, bool unit, const std::vector<double> &phi, int tile) {
     const int up_variant = (T.ncols <= 32) ? 2 : T.variant;
     const int tile_up = std::min(tile, tile_items_for(T.ncols, up_variant));
-    const int64_t ngroups = (int64_t)group_off.size() - 1;
-    // level state
-    std::vector<int64_t> goff = group_off;      // group offsets over this level's items
-    std::vector<int64_t> cnt = counts;          // per item counts (empty: all 1)
+    const int64_t ngroups = (int64_t)goff.size() - 1;
     int64_t nitems = items;
-    bool unit = counts.empty();
-    for (int level = 0; level < 64; ++level) {
+    for (int level = first; level < 64; ++level) {
         Level L;
         L.items = nitems;
         L.unit = unit;
@@ -304,6 +282,15 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
     return set_error(p, FIGARO_EUNSUPPORTED, "head/tail levels do not converge");
 }
 
+namespace {
+
+figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::vector<int64_t> &group_off,
+                         const std::vector<int64_t> &counts, const std::vector<double> &phi, int tile) {
+    return build_task_levels(p, T, 0, items, group_off, counts, counts.empty(), phi, tile);
+}
+
+}  // namespace
+
 figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total) {
     std::vector<int32_t> inv(n_total, -1);
     for (size_t q = 0; q < T.cols.size(); ++q) inv[T.cols[q]] = (int32_t)q;
@@ -311,6 +298,8 @@ figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total) {
     if (dev_upload(p, &T.d_inv_colmap, inv) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
     return FIGARO_OK;
 }
+
+namespace {
 
 // Phase timing of plan construction, printed to stderr when the environment
 // variable FIGARO_PLAN_TIMING is set.
@@ -423,6 +412,15 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     }
     p->n = n;
     if (n > kMaxCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 128 data columns in total");
+    // keys on the device: segmentation, counts and the tasks' first levels
+    // there (the host path below stays for host keys and analysis-only plans)
+    if (!keys_on_host && !p->analyze_only && !(opts && opts->host_plan)) {
+        p->device_plan = true;
+        figaro_status st = build_keys_on_device(p, rels, stream);
+        if (st != FIGARO_OK) return st;
+        timer.mark("plan on the device");
+        return finish_plan(p);
+    }
     // ---- keys to the host
     B.keys.resize(r);
     for (int i = 0; i < r; ++i) {
@@ -824,6 +822,13 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         }
     }
     timer.mark("tasks and uploads");
+    return finish_plan(p);
+}
+
+}  // namespace
+
+figaro_status finish_plan(figaro_plan_s *p) {
+    const int32_t n = p->n;
     // ---- stack rows (fused R's of every launch, then the root rows) and R0 rows
     int64_t srow = 0, r0row = 0;
     for (int v : p->post) {
@@ -894,7 +899,6 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
     return FIGARO_OK;
 }
 
-}  // namespace
 }  // namespace figaro
 
 using namespace figaro;
@@ -948,6 +952,7 @@ int64_t figaro_plan_workspace_bytes(figaro_plan_t p) { return p ? p->workspace_b
 
 figaro_status figaro_plan_permutation(figaro_plan_t p, int32_t i, int64_t *perm) {
     if (!p || i < 0 || i >= p->r || !perm) return set_error(p, FIGARO_EINVAL, "bad argument");
+    if (figaro_status st = fetch_host_arrays(p, i); st != FIGARO_OK) return st;
     std::memcpy(perm, p->rel[i].perm.data(), sizeof(int64_t) * p->rel[i].perm.size());
     return FIGARO_OK;
 }
@@ -960,6 +965,7 @@ int64_t figaro_plan_num_groups(figaro_plan_t p, int32_t i, int32_t which) {
 figaro_status figaro_plan_group_first_rows(figaro_plan_t p, int32_t i, int32_t which, int64_t *out) {
     if (!p || i < 0 || i >= p->r || !out || (which != 0 && which != 1))
         return set_error(p, FIGARO_EINVAL, "bad argument");
+    if (figaro_status st = fetch_host_arrays(p, i); st != FIGARO_OK) return st;
     const auto &R = p->rel[i];
     if (which == 0) {
         for (int64_t g = 0; g < R.G; ++g) out[g] = R.perm[R.seg_off[g]];
@@ -971,6 +977,7 @@ figaro_status figaro_plan_group_first_rows(figaro_plan_t p, int32_t i, int32_t w
 
 figaro_status figaro_plan_counts(figaro_plan_t p, int32_t i, figaro_count_kind kind, int64_t *out) {
     if (!p || i < 0 || i >= p->r || !out) return set_error(p, FIGARO_EINVAL, "bad argument");
+    if (figaro_status st = fetch_host_arrays(p, i); st != FIGARO_OK) return st;
     const auto &R = p->rel[i];
     const std::vector<int64_t> *v = nullptr;
     switch (kind) {
