@@ -307,10 +307,14 @@ const char *figaro_last_error(figaro_plan_t plan);
  *
  * figaro_r_backward_batched(): the same for figaro_r_backward, per instance.
  *
+ * Per-launch timing (figaro_profile_enable) must be disabled on every plan
+ * of a batch: figaro_r_batched(), figaro_r_backward_batched() and
+ * figaro_batch_capture() return FIGARO_EINVAL otherwise (a plan's timing
+ * events are recorded on one stream and read back on the host).
+ *
  * figaro_batch_capture(): captures the sequence of figaro_r_batched() with
  * these pointers into a HIP graph (stream capture on `stream`, which must not
- * be the null stream; profiling must be disabled on every plan), replacing
- * any graph captured before.  figaro_batch_launch() replays it on a stream:
+ * be the null stream), replacing any graph captured before.  figaro_batch_launch() replays it on a stream:
  * the buffers captured are read and written again.  Concurrent use of one
  * batch (or of its plans) must be serialised by the caller.
  */

@@ -56,6 +56,16 @@ double plan_cost(const figaro_plan_s *p) {
     return c + 1.0;
 }
 
+// Per-launch timing records events on the launch stream into a plan's pool
+// and reads them back on the host; a batch spreads its plans over several
+// streams, so batches refuse plans with timing enabled (eager passes and
+// capture alike).
+bool any_profiling(const figaro_batch_s *b) {
+    for (const figaro_plan_s *p : b->plans)
+        if (!p->prof_start.empty()) return true;
+    return false;
+}
+
 void release_graph(figaro_batch_s *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -164,6 +174,7 @@ int32_t figaro_batch_stream_of(figaro_batch_t b, int32_t i) {
 figaro_status figaro_r_batched(figaro_batch_t b, const double *const *const *values, const int64_t *const *ld,
                                double *const *R, hipStream_t stream) {
     if (!b || !values || !ld || !R) return batch_error(FIGARO_EINVAL, "NULL argument");
+    if (any_profiling(b)) return batch_error(FIGARO_EINVAL, "disable profiling on the batch's plans");
     return batch_pass(b, stream, [&](int i, hipStream_t t) {
         if (!values[i] || !ld[i] || !R[i]) return set_error(b->plans[i], FIGARO_EINVAL, "NULL argument");
         return run_forward(b->plans[i], values[i], ld[i], R[i], t);
@@ -176,6 +187,7 @@ figaro_status figaro_r_backward_batched(figaro_batch_t b, const double *const *c
                                         hipStream_t stream) {
     if (!b || !values || !ld || !R || !dR || !dvalues || !ld_dvalues)
         return batch_error(FIGARO_EINVAL, "NULL argument");
+    if (any_profiling(b)) return batch_error(FIGARO_EINVAL, "disable profiling on the batch's plans");
     return batch_pass(b, stream, [&](int i, hipStream_t t) {
         if (!values[i] || !ld[i] || !R[i] || !dR[i] || !dvalues[i] || !ld_dvalues[i])
             return set_error(b->plans[i], FIGARO_EINVAL, "NULL argument");

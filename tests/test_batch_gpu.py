@@ -113,6 +113,22 @@ def test_duplicate_plan_is_rejected(F, batch_setup):
     assert e.value.name == "EINVAL"
 
 
+def test_batch_refuses_profiled_plans(F, batch_setup):
+    """Per-launch timing of a plan is refused in batches (several streams),
+    eager passes included; the batch runs again once timing is off."""
+    insts, plans, vals = batch_setup
+    b = F.Batch(plans[:3])
+    plans[1].profile_enable(64)
+    try:
+        with pytest.raises(F.FigaroError) as e:
+            b.r(vals[:3])
+        assert e.value.name == "EINVAL"
+    finally:
+        plans[1].profile_enable(0)
+    b.r(vals[:3])
+    b.close()
+
+
 @pytest.mark.parametrize("i", [15, 35, 96])
 def test_autotuned_plan(F, oracle_lib, i):
     import torch
