@@ -254,57 +254,84 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
     return out
 
 
-def batched(F, count, steps, warmup):
-    """The batched workload: the first `count` instances (seeds 5000+i), one
-    plan each, run as one batch on 8 streams, eager and replayed from a
-    captured HIP graph, next to the same plans run one after another on one
-    stream."""
+def batched(F, count, steps, warmup, cache_path=None):
+    """The batched workload: instances 0..count-1 (seeds 5000+i), one plan
+    each, run as one batch on 8 streams, eager and replayed from a captured
+    HIP graph, next to the same plans run one after another on one stream.
+    The plans take the option set the autotuner picked for their shape class
+    (one representative tuned per class, kept in a JSON cache); the same
+    batch with default options is timed beside them."""
     import torch
     import synth
     ids = list(range(count))
-    insts = [synth.config5_instance(i) for i in ids]
-    log(f"batched: {len(insts)} instances, planning")
+    log(f"batched: generating {count} instances")
     t0 = time.perf_counter()
-    plans = [F.plan_from_instance(inst) for inst in insts]
+    views, cvals, M = [], [], 0
+    for i in ids:
+        inst = synth.config5_instance(i)
+        M += inst.M
+        views.append(F.instance_views(inst))
+        cvals.append([torch.as_tensor(np.ascontiguousarray(r.values)).cuda() for r in inst.rels])
+        del inst
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log("batched: tuning one instance per shape class")
+    cache = F.TuningCache(cache_path)
+    t0 = time.perf_counter()
+    opts = [cache.options(v, c) for v, c in zip(views, cvals)]
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    cache.save()
+    log(f"batched: planning ({len(cache.entries)} shape classes)")
+    t0 = time.perf_counter()
+    plans = [F.Plan(v, **o) for v, o in zip(views, opts)]
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    vals = [F.device_values(p, inst) for p, inst in zip(plans, insts)]
-    M = sum(inst.M for inst in insts)
-    b = F.Batch(plans, streams=8)
+    plans_d = [F.Plan(v) for v in views]
+    vals = [[p.to_plan_order(j, x) for j, x in enumerate(c)] for p, c in zip(plans, cvals)]
+    del cvals
+    torch.cuda.empty_cache()
+
+    def graph_time(pl):
+        b = F.Batch(pl, streams=8)
+        s = torch.cuda.Stream()
+        outs = [torch.empty((p.n, p.n), dtype=torch.float64, device="cuda") for p in pl]
+        with torch.cuda.stream(s):
+            b.capture(vals, outs, s)
+        s.synchronize()
+        for _ in range(warmup):
+            b.launch(s)
+        s.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.launch(s)
+        s.synchronize()
+        return (time.perf_counter() - t0) / steps, b
+
+    log("batched: timing")
+    t_graph, b = graph_time(plans)
     t_eager = time_steps(lambda: b.r(vals), steps, warmup)
-    s = torch.cuda.Stream()
-    outs = [torch.empty((p.n, p.n), dtype=torch.float64, device="cuda") for p in plans]
-    with torch.cuda.stream(s):
-        b.capture(vals, outs, s)
-    s.synchronize()
-
-    def replay():
-        b.launch(s)
-
-    for _ in range(warmup):
-        replay()
-    s.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        replay()
-    s.synchronize()
-    t_graph = (time.perf_counter() - t0) / steps
-    t_seq = time_steps(lambda: [p.r_factor(v) for p, v in zip(plans, vals)], steps, warmup)
 
     def fb():
         Rs = b.r(vals)
         return b.r_backward(vals, Rs, [loss_grad(R) for R in Rs])
 
     t_fb = time_steps(fb, max(2, steps // 2), 1)
+    t_seq = time_steps(lambda: [p.r_factor(v) for p, v in zip(plans, vals)], max(2, steps // 2), 1)
+    b.close()
+    t_graph_d, bd = graph_time(plans_d)
+    bd.close()
     out = {"workload": f"batched joins: instances 0..{count - 1} of the 512 (seeds 5000+i); 2-4 relations, "
                        "chains and stars, 1e3-1e6 tuples per relation, 4-32 columns per relation (n up to 128), "
                        "uniform or Zipf keys",
-           "instances": len(insts), "tuples": M, "plan_s": t_plan,
-           "fwd_ms_eager": t_eager * 1e3, "fwd_ms_graph": t_graph * 1e3, "fwd_ms_one_stream": t_seq * 1e3,
+           "instances": count, "tuples": M, "generate_s": t_gen, "plan_s": t_plan,
+           "tuning": {"shape_classes": len(cache.entries), "tune_s": t_tune,
+                      "classes": cache.entries},
+           "fwd_ms_graph": t_graph * 1e3, "fwd_ms_eager": t_eager * 1e3, "fwd_ms_one_stream": t_seq * 1e3,
+           "fwd_ms_graph_default_options": t_graph_d * 1e3,
            "fwd_tuples_per_s_graph": M / t_graph, "fwd_bwd_ms_eager": t_fb * 1e3,
            "fwd_bwd_tuples_per_s": M / t_fb}
-    b.close()
-    for p in plans:
+    for p in plans + plans_d:
         p.close()
     return out
 
@@ -331,8 +358,10 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--no-star", action="store_true")
     ap.add_argument("--no-tree-choice", action="store_true")
-    ap.add_argument("--batched", type=int, default=48,
+    ap.add_argument("--batched", type=int, default=512,
                     help="instances of the batched workload (the first N of 512; 0: skip)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON file of the autotuner's choice per shape class (read and updated)")
     ap.add_argument("--cpu-div", type=int, default=100)
     ap.add_argument("--comparator-div", type=int, default=200)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -422,7 +451,7 @@ def main():
     if not args.no_star:
         out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator, not args.no_tree_choice)
     if args.batched > 0:
-        out["batched"] = batched(F, args.batched, max(3, args.steps // 2), 2)
+        out["batched"] = batched(F, args.batched, max(3, args.steps // 4), 2, args.tuning_cache)
     if not args.no_comparator:
         log("comparator: materialised QR on a subsample")
         out["comparator"] = comparator(F, args.comparator_div)

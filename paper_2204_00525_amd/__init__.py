@@ -485,6 +485,50 @@ class _RelView:
         self.parent = parent
 
 
+def shape_class(relations) -> str:
+    """Tuning class of an instance: its total column count in the buckets of
+    the register tiles (8, 16, 32, 40, wider) and its tuple count in half
+    decades.  Instances of one class share the autotuner's choice."""
+    import math
+    n = sum(int(r.ncols) for r in relations)
+    m = sum(int(r.keys.shape[-1]) for r in relations)
+    nb = next((b for b in (8, 16, 32, 40) if n <= b), "wide")
+    return f"n{nb}_m{math.floor(2 * math.log10(max(m, 1))) / 2:.1f}"
+
+
+class TuningCache:
+    """The option set the autotuner (Plan.tuned) picks for each shape class,
+    tuned on the first instance of the class that asks and kept in a JSON
+    file (path None: in memory only)."""
+
+    def __init__(self, path=None):
+        import json
+        self.path = path
+        self.entries = {}
+        if path and os.path.exists(path):
+            with open(path) as f:
+                self.entries = json.load(f)
+
+    def options(self, relations, values, reps: int = 2) -> dict:
+        """Options (tile_items, waves_per_task, variant) for an instance:
+        from the cache, or by tuning it (values: caller order, as for
+        Plan.tuned)."""
+        key = shape_class(relations)
+        if key not in self.entries:
+            p = Plan.tuned(relations, values, reps=reps)
+            opts, ms = p.tuning()
+            p.close()
+            self.entries[key] = dict(opts, ms=ms)
+        e = self.entries[key]
+        return {k: int(e[k]) for k in ("tile_items", "waves_per_task", "variant")}
+
+    def save(self):
+        import json
+        if self.path:
+            with open(self.path, "w") as f:
+                json.dump(self.entries, f, indent=1, sort_keys=True)
+
+
 def instance_views(inst, device="cuda") -> List:
     """Relation views (keys on the device) of a synth.Instance-like object."""
     import torch
