@@ -206,6 +206,36 @@ def plan_times(F, inst):
     return plan, t_dev, t_host
 
 
+def svd_pca(F, plan, vals, R, warmup, k=8):
+    """From R to the SVD and PCA of the star join (section "From R to Q,
+    SVD and PCA"): the SVD of R on the device, then the rank-k PCA
+    projection A V[:, :k] of all 10^7 join rows and the rows of Q = A R^-1,
+    enumerated without materialising A."""
+    import torch
+
+    def timed(fn, reps=3):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, out
+
+    t_svd, (s, U, V) = timed(lambda: F.svd_of_r(R))
+    t_pca, P = timed(lambda: plan.join_multiply(vals, V[:, :k]))
+    Rinv = F.r_inverse(R)
+    t_q, Q = timed(lambda: plan.join_multiply(vals, Rinv), reps=2)
+    rows = int(plan.join_rows)
+    ortho = float(torch.linalg.norm(Q.T @ Q - torch.eye(plan.n, dtype=torch.float64, device="cuda")))
+    del Q, P
+    torch.cuda.empty_cache()
+    return {"svd_of_r_ms": t_svd * 1e3, "sigma_max": float(s[0]), "sigma_min": float(s[-1]),
+            "pca_k": k, "pca_projection_ms": t_pca * 1e3, "pca_rows_per_s": rows / t_pca,
+            "q_rows_ms": t_q * 1e3, "q_rows_per_s": rows / t_q, "q_orthogonality": ortho}
+
+
 def star(F, steps, warmup, with_comparator, with_tree_choice=True):
     """Key/foreign-key star join: forward, forward+backward, comparator, join
     tree choice."""
@@ -226,6 +256,7 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
            "fwd_bwd_ms": t_fb * 1e3, "fwd_bwd_tuples_per_s": inst.M / t_fb}
     if with_tree_choice:
         out["tree_choice"] = tree_choice(F, inst, R, t_fwd, steps, warmup)
+    out["svd_pca"] = svd_pca(F, plan, vals, R, warmup)
     if with_comparator:
         log("star join: materialising 10^7 x 40 for the comparator")
         t0 = time.perf_counter()

@@ -260,6 +260,48 @@ figaro_status figaro_tsqr_noalloc(int64_t rows, int32_t n, const double *A, int6
                                   hipStream_t stream);
 
 /*
+ * From R to Q, SVD and PCA (section "From R to Q, SVD and PCA").
+ *
+ * figaro_svd_r(): R = U_R Sigma V^T for an n x n matrix R (device, column-
+ * major, 1 <= n <= 128), by one-sided Jacobi rotations; sigma (device [n])
+ * in decreasing order, V and U_R (device n x n column-major; U may be NULL)
+ * with matching columns.  For the R of a join matrix A, sigma and V are the
+ * singular values and right singular vectors of A, and V's columns its
+ * principal components.  Each column of U_R and V is determined up to sign
+ * (up to a rotation within repeated singular values).  work: device, at
+ * least 2 n^2 doubles, overwritten.  Enqueued on `stream`.
+ *
+ * figaro_r_inverse(): R^-1 of an upper-triangular n x n R with non-zero
+ * diagonal (device, column-major), enqueued on `stream`.
+ *
+ * figaro_join_multiply(): rows row0 .. row0 + nrows - 1 of A M, for the join
+ * matrix A of the plan (never materialised) and an n x k matrix M (device,
+ * column-major, leading dimension ldm >= n, 1 <= k <= 128), each column c
+ * multiplied by col_scale[c] when col_scale (device [k]) is not NULL:
+ * out (device, column-major [k][ld_out], ld_out >= nrows).  With M = R^-1
+ * the rows are those of Q (A = QR); with M = V and col_scale = 1 / sigma
+ * those of the left singular vectors U; with M = V[:, :k] the PCA
+ * projection.  The join rows come in a fixed order: root key groups in
+ * plan order; within a key group its tuples in plan order, each followed by
+ * the combinations of its children's subtree rows (first child slowest).
+ * tuple_ids (device int64 [r][ld_ids], may be NULL) receives, for every
+ * output row, the caller row index of the tuple each relation contributes.
+ * values / ld as for figaro_r (plan order).  work: device, at least
+ * figaro_join_multiply_workspace_bytes(plan, k) bytes (the dot products of
+ * every tuple with the rows of M).  At most 16 relations.  Enqueued on
+ * `stream`; no allocation.
+ */
+figaro_status figaro_svd_r(int32_t n, const double *R, double *sigma, double *U, double *V, double *work,
+                           hipStream_t stream);
+figaro_status figaro_r_inverse(int32_t n, const double *R, double *Rinv, hipStream_t stream);
+int64_t figaro_join_multiply_workspace_bytes(figaro_plan_t plan, int32_t k);   /* -1 on error */
+figaro_status figaro_join_multiply(figaro_plan_t plan, const double *const *values, const int64_t *ld,
+                                   const double *M, int64_t ldm, int32_t k, const double *col_scale,
+                                   int64_t row0, int64_t nrows, double *out, int64_t ld_out,
+                                   int64_t *tuple_ids, int64_t ld_ids, void *work, int64_t work_bytes,
+                                   hipStream_t stream);
+
+/*
  * Per-kernel timing for benchmarks.  While enabled, the compute calls record a
  * pair of HIP events on the caller's stream around every kernel launch, in a
  * pool of `capacity` pairs (events are created here, not in the compute

@@ -22,6 +22,9 @@ Contents, each following one passage of the paper:
   * gen_head, gen_tail       Definition 2 (generalized head and tail)
   * rotations_lemma          the explicit rotation sequence of Lemmas 1 and 2
   * brute_counts             the count queries of Fig. 4 by brute force
+  * q_of_join, svd_of_join   section "From R to Q, SVD and PCA": Q = A R^-1
+                             of the materialised join (R from r_of_join),
+                             the SVD of the materialised join by LAPACK
   * figaro_alg3              Algorithm 3 (heads_and_tails,
                              process_and_join_children,
                              project_away_join_attributes) in the paper's order
@@ -570,3 +573,23 @@ def grad_logdet_closed_form(inst):
         out.append(g)
         c0 += rel.ncols
     return out
+
+
+def q_of_join(inst) -> Tuple[np.ndarray, np.ndarray]:
+    """Q = A R^-1 by its definition (section "From R to Q, SVD and PCA"):
+    the materialised join A, R from r_of_join, a triangular solve
+    R^T Q^T = A^T.  Returns (Q, the join's tuple indices per row)."""
+    import scipy.linalg
+    A = join(inst)
+    R = r_of_join(inst)
+    Q = scipy.linalg.solve_triangular(R, A.T, trans="T", lower=False).T
+    return Q, join_indices(inst)
+
+
+def svd_of_join(inst) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+    """The SVD A = U diag(sigma) V^T of the materialised join (LAPACK, thin),
+    sigma decreasing.  Returns (U, sigma, V, the join's tuple indices)."""
+    A = join(inst)
+    U, s, Vt = np.linalg.svd(np.ascontiguousarray(A), full_matrices=False)
+    return U, s, Vt.T, join_indices(inst)
+

@@ -103,6 +103,10 @@ def lib():
         "figaro_tsqr_workspace_bytes": (i64, [i64, i32]),
         "figaro_tsqr": (i32, [i64, i32, vp, i64, vp, vp, i64, vp]),
         "figaro_tsqr_noalloc": (i32, [i64, i32, vp, i64, vp, vp]),
+        "figaro_svd_r": (i32, [i32, vp, vp, vp, vp, vp, vp]),
+        "figaro_r_inverse": (i32, [i32, vp, vp, vp]),
+        "figaro_join_multiply_workspace_bytes": (i64, [vp, i32]),
+        "figaro_join_multiply": (i32, [vp, pp, pi64, vp, i64, i32, vp, i64, i64, vp, i64, vp, i64, vp, i64, vp]),
         "figaro_join_tree_cost": (i32, [i32, ctypes.POINTER(RelationDesc), i32, ctypes.POINTER(dbl), vp]),
         "figaro_choose_join_tree": (i32, [i32, ctypes.POINTER(RelationDesc), i32, ctypes.POINTER(i32),
                                           ctypes.POINTER(dbl), vp]),
@@ -366,6 +370,34 @@ class Plan:
                               _stream_handle(stream)), self._handle)
         return out.T
 
+    def join_multiply(self, values: List, M, col_scale=None, row0: int = 0, nrows=None, with_ids: bool = False,
+                      stream=None):
+        """Rows row0 .. row0 + nrows - 1 of A M for the join matrix A (never
+        materialised) and an n x k device matrix M, columns scaled by
+        col_scale; with with_ids also the caller row index of every
+        relation's tuple in each row ((r, nrows) int64).  Returns the
+        (nrows, k) rows (and the ids)."""
+        import torch
+        ptrs, lds = self._value_args(values)
+        if nrows is None:
+            nrows = int(self.join_rows) - row0
+        k = int(M.shape[1])
+        Mc = M.detach().to(torch.float64).T.contiguous()      # column-major n x k
+        dev = values[0].device
+        nbytes = int(lib().figaro_join_multiply_workspace_bytes(self._handle, k))
+        work = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
+        out = torch.empty((k, max(nrows, 1)), dtype=torch.float64, device=dev)
+        ids = torch.empty((self.r, max(nrows, 1)), dtype=torch.int64, device=dev) if with_ids else None
+        sc = col_scale.detach().to(torch.float64).contiguous() if col_scale is not None else None
+        _check(lib().figaro_join_multiply(self._handle, ptrs, lds, ctypes.c_void_p(Mc.data_ptr()), self.n, k,
+                                          ctypes.c_void_p(sc.data_ptr()) if sc is not None else None, row0, nrows,
+                                          ctypes.c_void_p(out.data_ptr()), max(nrows, 1),
+                                          ctypes.c_void_p(ids.data_ptr()) if ids is not None else None,
+                                          max(nrows, 1), ctypes.c_void_p(work.data_ptr()), work.numel() * 8,
+                                          _stream_handle(stream)), self._handle)
+        rows = out[:, :nrows].T
+        return (rows, ids[:, :nrows]) if with_ids else rows
+
     def r_backward(self, values: List, R, dR, stream=None):
         """Gradients of a loss with respect to the values (plan order), given
         R from r_factor() and dR = dLoss/dR (only its upper triangle is used)."""
@@ -621,6 +653,35 @@ def debug_dense_step(A, workgroups: int, tiles_per_wave: int, variant: int = 0, 
                                          tiles_per_wave, variant, ctypes.c_void_p(out.data_ptr()), workgroups * n,
                                          None, _stream_handle(stream)), None)
     return out.t()
+
+
+def svd_of_r(R, stream=None):
+    """sigma (decreasing), U_R and V of an n x n device matrix R (the R of a
+    join: sigma and V are then the join matrix's singular values and right
+    singular vectors)."""
+    import torch
+    n = int(R.shape[0])
+    Rc = R.detach().T.contiguous()
+    dev = R.device
+    sigma = torch.empty(n, dtype=torch.float64, device=dev)
+    U = torch.empty((n, n), dtype=torch.float64, device=dev)
+    V = torch.empty((n, n), dtype=torch.float64, device=dev)
+    work = torch.empty(2 * n * n, dtype=torch.float64, device=dev)
+    _check(lib().figaro_svd_r(n, ctypes.c_void_p(Rc.data_ptr()), ctypes.c_void_p(sigma.data_ptr()),
+                              ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(V.data_ptr()),
+                              ctypes.c_void_p(work.data_ptr()), _stream_handle(stream)), None)
+    return sigma, U.T, V.T
+
+
+def r_inverse(R, stream=None):
+    """R^-1 of an upper-triangular n x n device matrix."""
+    import torch
+    n = int(R.shape[0])
+    Rc = R.detach().T.contiguous()
+    X = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    _check(lib().figaro_r_inverse(n, ctypes.c_void_p(Rc.data_ptr()), ctypes.c_void_p(X.data_ptr()),
+                                  _stream_handle(stream)), None)
+    return X.T
 
 
 def _colmajor(A):

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfigaro.so")
-SOURCES = ["plan.cpp", "run.cpp", "batch.cpp", "kernels.hip", "backward.hip", "tsqr.hip", "treeplan.cpp", "dplan.hip"]
+SOURCES = ["plan.cpp", "run.cpp", "batch.cpp", "kernels.hip", "backward.hip", "tsqr.hip", "treeplan.cpp", "dplan.hip", "beyond.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

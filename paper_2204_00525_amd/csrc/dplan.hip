@@ -1154,6 +1154,20 @@ figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc 
     return check_launch(p);
 }
 
+figaro_status enumeration_arrays(figaro_plan_s *p, hipStream_t s) {
+    Temp T;
+    for (auto &R : p->rel) {
+        if (dev_alloc(p, (void **)&R.d_theta_excl, sizeof(int64_t) * (size_t)(R.G + 1)) != hipSuccess)
+            return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        int64_t *pad = T.get<int64_t>(R.G + 1);
+        DP_LAUNCH(k_copy_i64, R.G, R.d_theta, pad, R.G);
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, pad + R.G, (int64_t)0);
+        scan_excl(pad, R.d_theta_excl, R.G + 1, T, s);
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return set_error(p, FIGARO_EHIP, "hipStreamSynchronize failed");
+    return check_launch(p);
+}
+
 figaro_status fetch_host_arrays(figaro_plan_s *p, int32_t i) {
     auto &R = p->rel[i];
     if (R.host_arrays) return FIGARO_OK;

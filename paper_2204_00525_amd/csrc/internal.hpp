@@ -336,6 +336,7 @@ struct RelPlan {
     // the host copies above are fetched when a query asks for them
     int64_t *d_seg_off = nullptr, *d_par_off = nullptr;   // [G+1], [P+1]
     int64_t *d_theta = nullptr, *d_phi_circ = nullptr;     // [G]
+    int64_t *d_theta_excl = nullptr;  // [G+1] exclusive prefix sums of Theta (join-row enumeration)
     int64_t *d_phi_up = nullptr, *d_phi_down = nullptr;   // [P]
     bool host_arrays = true;         // perm, seg_off, par_off and the counts are on the host
 };
@@ -436,5 +437,9 @@ figaro_status finish_plan(figaro_plan_s *p);
 figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc *rels, hipStream_t stream);
 // Host copies of the device plan's arrays for the query calls.
 figaro_status fetch_host_arrays(figaro_plan_s *p, int32_t rel);
+// Device arrays the enumeration of join rows reads (segment and parent-group
+// offsets, Theta and its prefix sums, Phi-down), for plans of either builder
+// (dplan.hip).
+figaro_status enumeration_arrays(figaro_plan_s *p, hipStream_t stream);
 
 }  // namespace figaro

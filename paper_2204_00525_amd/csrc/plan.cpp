@@ -829,6 +829,18 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
 
 figaro_status finish_plan(figaro_plan_s *p) {
     const int32_t n = p->n;
+    // the arrays the join-row enumeration reads: a host-built plan copies its
+    // offsets and counts over (a device-built plan has them there)
+    if (!p->device_plan) {
+        for (auto &R : p->rel) {
+            if (dev_upload(p, &R.d_seg_off, R.seg_off) != hipSuccess || dev_upload(p, &R.d_theta, R.theta) != hipSuccess)
+                return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            if (R.parent >= 0 && (dev_upload(p, &R.d_par_off, R.par_off) != hipSuccess ||
+                                  dev_upload(p, &R.d_phi_down, R.phi_down) != hipSuccess))
+                return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        }
+    }
+    if (figaro_status st = enumeration_arrays(p, 0); st != FIGARO_OK) return st;
     // ---- stack rows (fused R's of every launch, then the root rows) and R0 rows
     int64_t srow = 0, r0row = 0;
     for (int v : p->post) {

@@ -412,3 +412,45 @@ def test_gradient_references_agree(oracle_lib, maker):
     g_closed = oracle_lib.grad_logdet_closed_form(inst)
     for a, b in zip(g_auto, g_closed):
         assert _relf(a, b) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Q, SVD and PCA of the join (section "From R to Q, SVD and PCA")
+# ---------------------------------------------------------------------------
+
+BEYOND = [lambda: synth.config1(), lambda: synth.paper_fig3(5, m=(40, 90, 30, 30), n=(3, 2, 4, 1), dom=3),
+          lambda: synth.random_chain(3, 3, 60, 2, 6), lambda: synth.random_star(4, 4, 80, 10, 2)]
+
+
+@pytest.mark.parametrize("maker", BEYOND)
+def test_q_of_join_is_orthonormal_and_reproduces_the_join(oracle_lib, maker):
+    inst = maker()
+    Q, ids = oracle_lib.q_of_join(inst)
+    A = oracle_lib.join(inst)
+    R = oracle_lib.r_of_join(inst)
+    n = inst.n
+    assert Q.shape == A.shape and ids.shape == (inst.r, A.shape[0])
+    # rounding of sums over the join rows grows like their square root
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * np.sqrt(A.shape[0]) * n
+    assert np.linalg.norm(Q @ R - A) <= 1e-13 * np.linalg.norm(A)
+
+
+@pytest.mark.parametrize("maker", BEYOND)
+def test_svd_of_join_matches_its_invariants(oracle_lib, maker):
+    """U^T U = I, U diag(sigma) V^T = A, sigma decreasing, sigma^2 the
+    eigenvalues of A^T A (long double Gram), and the singular values and
+    right singular vectors of A those of R (the paper's second step)."""
+    inst = maker()
+    U, s, V, ids = oracle_lib.svd_of_join(inst)
+    A = oracle_lib.join(inst)
+    n = inst.n
+    assert np.all(np.diff(s) <= 0)
+    assert np.linalg.norm(U.T @ U - np.eye(n)) <= 1e-14 * np.sqrt(A.shape[0]) * n
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 1e-12
+    assert np.linalg.norm((U * s) @ V.T - A) <= 1e-13 * np.linalg.norm(A)
+    Ghi, Glo = oracle_lib.gram_ld(A)
+    ev = np.sort(np.linalg.eigvalsh(Ghi + Glo))[::-1]
+    assert np.max(np.abs(s ** 2 - ev)) <= 1e-12 * ev[0]
+    R = oracle_lib.r_of_join(inst)
+    sr = np.linalg.svd(R, compute_uv=False)
+    assert np.max(np.abs(sr - s)) <= 1e-11 * s[0]
