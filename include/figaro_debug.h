@@ -14,7 +14,8 @@ extern "C" {
 /* Run the forward pass up to (not including) the post-processing TSQR and
  * copy the stack of partial R factors and root rows to the host:
  * host_out receives figaro_debug_stack_rows() rows of n columns, column-major
- * with leading dimension figaro_debug_stack_rows().  Synchronises `stream`. */
+ * with leading dimension figaro_debug_stack_rows().  Synchronises `stream`.
+ * FIGARO_EUNSUPPORTED for plans of more than 128 columns. */
 int64_t figaro_debug_stack_rows(figaro_plan_t plan);
 figaro_status figaro_debug_stack(figaro_plan_t plan, const double *const *values, const int64_t *ld,
                                  double *host_out, hipStream_t stream);
@@ -41,7 +42,8 @@ figaro_status figaro_debug_dense_step(int32_t n, int64_t rows, const double *in,
                                       double *out, int64_t ld_out, double *final_r, hipStream_t stream);
 
 /* Layout of the stack: up to max_regions triples (block id, first row, rows)
- * written to regions_host; returns the number of regions. */
+ * written to regions_host; returns the number of regions (-1 for plans of
+ * more than 128 columns, which reduce their stack in place). */
 int32_t figaro_debug_stack_layout(figaro_plan_t plan, int64_t *regions_host, int32_t max_regions);
 
 #ifdef __cplusplus

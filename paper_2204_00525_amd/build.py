@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfigaro.so")
-SOURCES = ["plan.cpp", "run.cpp", "batch.cpp", "kernels.hip", "backward.hip", "tsqr.hip", "treeplan.cpp", "dplan.hip", "beyond.hip"]
+SOURCES = ["plan.cpp", "run.cpp", "batch.cpp", "kernels.hip", "backward.hip", "tsqr.hip", "treeplan.cpp", "dplan.hip", "beyond.hip",
+           "wideqr.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -44,7 +45,10 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if p.wait() != 0:
             raise RuntimeError("compile failed: " + " ".join(c))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    # rocBLAS: the plain GEMMs of the blocked QR's trailing updates
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(HIPCC)), "lib")
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L" + rocm_lib, "-Wl,-rpath," + rocm_lib, "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

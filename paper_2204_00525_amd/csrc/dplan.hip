@@ -1065,9 +1065,11 @@ figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc 
             if ((st = finish_task(p, R.a2, n)) != FIGARO_OK) return st;
         }
         if (!R.children.empty()) {
+            R.col_src.assign(R.nsub, -1);
+            R.col_idx.assign(R.nsub, 0);
             for (int c = 0; c < R.ncols; ++c) {
                 R.col_src[R.own_pos + c] = -1;
-                R.col_idx[R.own_pos + c] = (int8_t)c;
+                R.col_idx[R.own_pos + c] = (int16_t)c;
             }
             std::vector<double *> mults(R.children.size(), nullptr);
             if (dev_alloc(p, (void **)&R.d_own_mult, sizeof(double) * (size_t)R.G) != hipSuccess)
@@ -1086,15 +1088,20 @@ figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc 
                 int32_t *dp = nullptr;
                 if (dev_upload(p, &dp, pos) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
                 for (size_t q = 0; q < pos.size(); ++q) {
-                    R.col_src[pos[q]] = (int8_t)c;
-                    R.col_idx[pos[q]] = (int8_t)q;
+                    R.col_src[pos[q]] = (int16_t)c;
+                    R.col_idx[pos[q]] = (int16_t)q;
                 }
                 R.d_cidx.push_back(D.cidx[v][c]);
                 R.d_mult.push_back(mults[c]);
                 R.d_colpos.push_back(dp);
             }
+            if (dev_upload(p, &R.d_col_src, R.col_src) != hipSuccess ||
+                dev_upload(p, &R.d_col_idx, R.col_idx) != hipSuccess)
+                return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            // (the in-place view carries its column codes by value: at most
+            // kMaxCols subtree columns)
             R.fuse_join = R.parent >= 0 && R.P < R.G && R.children.size() <= (size_t)kFuseMaxChildren &&
-                          !p->separate_join;
+                          R.nsub <= kMaxCols && !p->separate_join;
             if (R.fuse_join)
                 for (int ch : R.children) {
                     double *rm;

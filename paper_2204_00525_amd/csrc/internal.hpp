@@ -12,8 +12,12 @@
 
 namespace figaro {
 
-// Widest column count the register-tile kernels handle.
+// Widest column count the register-tile kernels handle (the narrow regime:
+// dense TSQR of the stack in registers, backward pass).
 constexpr int kMaxCols = 128;
+// Widest column count of a plan; above kMaxCols the stack is reduced by the
+// blocked Householder QR of wideqr.hip.
+constexpr int kMaxWideCols = 16384;
 // Head/tail tasks with more columns than this write their tails to the stack
 // of the post-processing TSQR, in column chunks of kChunkCols, instead of
 // folding them into a register-tile QR.
@@ -82,7 +86,7 @@ struct HelmertArgs {
     int64_t stack_row0;
     int32_t n_total;
     uint64_t other_cols[2];      // bit g set: global column g is not a column of this block
-    uint8_t colmap[kMaxCols];    // global column of every local column
+    uint16_t colmap[kFusedMaxCols];   // output column of every local column
     // R0 output (materialisation for inspection)
     double *r0;
     int64_t ld_r0;
@@ -163,8 +167,8 @@ struct JoinArgs {
     const int32_t *colpos[kMaxChildren];
     const int32_t *cidx[kMaxChildren];
     const double *mult[kMaxChildren];
-    int8_t col_src[kMaxCols];    // per output column: -1 own, else the child
-    int8_t col_idx[kMaxCols];    // per output column: column within its source
+    const int16_t *col_src;      // [nsub] per output column: -1 own, else the child
+    const int16_t *col_idx;      // [nsub] per output column: column within its source
 };
 
 // Root emit: rows s[.][g] / sqrt(c_g) into the stack (or R0).
@@ -220,6 +224,8 @@ struct RootBwdArgs {
     int32_t ds_rowmajor;         // 1: group g, column c at ds[g * ld_ds + c]
 };
 
+struct WideQr;
+
 // ---------------------------------------------------------------------------
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
@@ -240,6 +246,16 @@ hipError_t launch_root_bwd(const RootBwdArgs &a, hipStream_t s);
 hipError_t launch_copy_cols(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t rows,
                             int32_t ncols, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+// Blocked Householder QR (wideqr.hip).
+int64_t wide_qr_panel_rows(int64_t h, int32_t n, bool tp);
+int64_t wide_qr_workspace_doubles(int64_t max_nv, int32_t n);
+figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, std::string &err);
+void wide_qr_release(WideQr &w);
+figaro_status wide_qr(const WideQr &w, double *A, int64_t lda, int64_t h, int32_t n, bool tp, hipStream_t s,
+                      std::string &err);
+hipError_t launch_copy_upper(const double *src, int64_t ld_src, int64_t rows, int32_t cols, double *dst,
+                             int64_t ld_dst, int64_t row0, int64_t col0, hipStream_t s);
+hipError_t launch_final_r(const double *A, int64_t lda, int64_t rows, int32_t n, double *R, hipStream_t s);
 // Whole passes on one plan (run.cpp), used by the batched entry points.
 figaro_status run_forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, double *R,
                           hipStream_t s);
@@ -278,6 +294,10 @@ struct Level {
 // heads_and_tails (A2) or project_away_join_attributes (A4) of one relation.
 struct Task {
     bool active = false;
+    // wide plans: the tails of a wide heads_and_tails task go to a region
+    // of their own (task columns, ld region_ld) that is reduced by itself
+    double *d_region = nullptr;
+    int64_t region_ld = 0;
     int32_t variant = 0;          // tile shape of the head/tail kernel
     int32_t ncols = 0;
     int32_t block_id = 0;
@@ -318,8 +338,9 @@ struct RelPlan {
     std::vector<double *> d_mult;
     std::vector<int32_t *> d_colpos;
     std::vector<double *> d_sigma_rm;   // fused join: row-major copy of every child's sums [P_child][nsub_child]
-    int8_t col_src[kMaxCols] = {};   // per subtree column: -1 own, else child index
-    int8_t col_idx[kMaxCols] = {};   // per subtree column: column within its source
+    std::vector<int16_t> col_src;    // [nsub] per subtree column: -1 own, else child index
+    std::vector<int16_t> col_idx;    // [nsub] per subtree column: column within its source
+    int16_t *d_col_src = nullptr, *d_col_idx = nullptr;
     bool fuse_join = false;          // joined heads read in place by the first project-away level
     double *d_s = nullptr;           // [nsub][ld_s]
     int64_t ld_s = 0;                // G rounded up to 16 (aligned columns)
@@ -349,6 +370,19 @@ struct ProfPending {
     double bytes, flops;
 };
 
+// Workspace of the blocked Householder QR (wideqr.hip).
+struct WideQr {
+    double *V = nullptr;      // [32][ldv] reflectors of one panel (virtual rows)
+    int64_t ldv = 0;
+    double *tau = nullptr;    // [n]
+    double *T = nullptr;      // [32][32]
+    double *G = nullptr;      // [32][32]
+    double *W = nullptr;      // [n][32]
+    double *part = nullptr;   // partial sums of the per-column passes
+    double *head = nullptr;
+    void *blas = nullptr;     // rocblas_handle
+};
+
 struct DenseLevel {
     int64_t rows;
     int32_t waves;
@@ -376,6 +410,11 @@ struct figaro_plan_s {
     double *d_stack[2] = {nullptr, nullptr};
     int64_t stack_ld[2] = {0, 0};
     std::vector<figaro::DenseLevel> dense;
+    // wide regime (n > kMaxCols): rows [0, n) of stack 0 hold the R's of the
+    // wide heads_and_tails tasks on the diagonal, the other stack rows
+    // follow; the whole stack is reduced by the blocked QR
+    bool wide = false;
+    figaro::WideQr wqr;
     int64_t r0_rows = 0;
     double *d_K = nullptr;           // n x n, backward
     double *d_W = nullptr;           // n x n scratch of the QR adjoint

@@ -411,7 +411,8 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
         n += p->rel[i].ncols;
     }
     p->n = n;
-    if (n > kMaxCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 128 data columns in total");
+    if (n > kMaxWideCols) return set_error(p, FIGARO_EUNSUPPORTED, "more than 16384 data columns in total");
+    p->wide = n > kMaxCols;
     // keys on the device: segmentation, counts and the tasks' first levels
     // there (the host path below stays for host keys and analysis-only plans)
     if (!keys_on_host && !p->analyze_only && !(opts && opts->host_plan)) {
@@ -726,9 +727,11 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             if ((st = finish_task(p, R.a2, n)) != FIGARO_OK) return st;
         }
         if (!R.children.empty()) {
+            R.col_src.assign(R.nsub, -1);
+            R.col_idx.assign(R.nsub, 0);
             for (int c = 0; c < R.ncols; ++c) {
                 R.col_src[R.own_pos + c] = -1;
-                R.col_idx[R.own_pos + c] = (int8_t)c;
+                R.col_idx[R.own_pos + c] = (int16_t)c;
             }
             std::vector<double> own(R.G);
             std::vector<std::vector<double>> mult(R.children.size(), std::vector<double>(R.G));
@@ -757,8 +760,8 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
                                             R.sub_cols.begin()));
                 if (dev_upload(p, &dp, pos) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
                 for (size_t q = 0; q < pos.size(); ++q) {
-                    R.col_src[pos[q]] = (int8_t)c;
-                    R.col_idx[pos[q]] = (int8_t)q;
+                    R.col_src[pos[q]] = (int16_t)c;
+                    R.col_idx[pos[q]] = (int16_t)q;
                 }
                 R.d_cidx.push_back(di);
                 R.d_mult.push_back(dm);
@@ -770,8 +773,13 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
             // projects its join attributes away in place (first head/tail
             // level) when it has at most kFuseMaxChildren children; the
             // backward pass, which reads them twice, stores them
+            if (dev_upload(p, &R.d_col_src, R.col_src) != hipSuccess ||
+                dev_upload(p, &R.d_col_idx, R.col_idx) != hipSuccess)
+                return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+            // (the in-place view carries its column codes by value: at most
+            // kMaxCols subtree columns)
             R.fuse_join = R.parent >= 0 && R.P < R.G && R.children.size() <= (size_t)kFuseMaxChildren &&
-                          !p->separate_join;
+                          R.nsub <= kMaxCols && !p->separate_join;
             if (R.fuse_join)
                 for (int ch : R.children) {
                     double *rm;
@@ -842,22 +850,39 @@ figaro_status finish_plan(figaro_plan_s *p) {
     }
     if (figaro_status st = enumeration_arrays(p, 0); st != FIGARO_OK) return st;
     // ---- stack rows (fused R's of every launch, then the root rows) and R0 rows
-    int64_t srow = 0, r0row = 0;
+    // Wide plans keep the stack's first n rows for the R's of their wide
+    // heads_and_tails tasks, whose tails go to regions of their own.
+    int64_t srow = p->wide ? n : 0, r0row = 0;
+    std::vector<Task *> regions;
+    int64_t region_doubles = 0, max_panel_rows = 0;
     for (int v : p->post) {
         auto &R = p->rel[v];
         for (Task *T : {&R.a2, &R.a4}) {
             if (!T->active) continue;
+            const bool region = p->wide && T == &R.a2 && T->ncols > kFusedMaxCols;
+            int64_t rrow = 0;
             for (auto &L : T->levels) {
-                L.stack_row0 = srow;
-                // the first level folds its tails into one R per workgroup;
-                // the upper levels hold few rows and append their tails as
-                // is, and so do all levels of a wide task
-                if (&L == &T->levels[0] && T->ncols <= kFusedMaxCols)
-                    srow += (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols;
-                else
-                    srow += L.items;
+                if (region) {
+                    L.stack_row0 = rrow;
+                    rrow += L.items;
+                } else {
+                    L.stack_row0 = srow;
+                    // the first level folds its tails into one R per
+                    // workgroup; the upper levels hold few rows and append
+                    // their tails as is, and so do all levels of a wide task
+                    if (&L == &T->levels[0] && T->ncols <= kFusedMaxCols)
+                        srow += (int64_t)((L.waves + waves_per_block() - 1) / waves_per_block()) * T->ncols;
+                    else
+                        srow += L.items;
+                }
                 L.r0_row0 = r0row;
                 r0row += L.items;
+            }
+            if (region) {
+                T->region_ld = std::max<int64_t>(rrow, 1);
+                region_doubles += T->region_ld * T->ncols;
+                max_panel_rows = std::max(max_panel_rows, wide_qr_panel_rows(T->region_ld, T->ncols, false));
+                regions.push_back(T);
             }
         }
         if (R.parent < 0) {
@@ -869,6 +894,26 @@ figaro_status finish_plan(figaro_plan_s *p) {
     }
     p->stack_rows = srow;
     p->r0_rows = r0row;
+    if (p->wide) {
+        max_panel_rows = std::max(max_panel_rows, wide_qr_panel_rows(srow, n, true));
+        p->stack_ld[0] = std::max<int64_t>(srow, 1);
+        double *ws = nullptr, *reg = nullptr;
+        if (dev_alloc(p, (void **)&p->d_stack[0], sizeof(double) * (size_t)n * (size_t)p->stack_ld[0]) !=
+                hipSuccess ||
+            dev_alloc(p, (void **)&reg, sizeof(double) * (size_t)region_doubles) != hipSuccess ||
+            dev_alloc(p, (void **)&ws, sizeof(double) * (size_t)wide_qr_workspace_doubles(max_panel_rows, n)) !=
+                hipSuccess ||
+            dev_alloc(p, (void **)&p->d_status, sizeof(int32_t) * 4) != hipSuccess)
+            return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        for (Task *T : regions) {
+            T->d_region = reg;
+            reg += T->region_ld * T->ncols;
+        }
+        std::string err;
+        if (figaro_status st = wide_qr_init(p->wqr, ws, max_panel_rows, n, err); st != FIGARO_OK)
+            return set_error(p, st, err);
+        return FIGARO_OK;
+    }
     // dense TSQR levels over the stack: a workgroup folds tiles_per_wave
     // steps of wpb tiles (wpb waves on separate tiles; one shared tile for
     // n > 16) into one R of n rows, so each level divides the rows by
@@ -946,6 +991,7 @@ void figaro_plan_destroy(figaro_plan_t p) {
     if (!p) return;
     for (auto e : p->prof_start) (void)hipEventDestroy(e);
     for (auto e : p->prof_stop) (void)hipEventDestroy(e);
+    wide_qr_release(p->wqr);
     for (void *a : p->allocations) (void)hipFree(a);
     delete p;
 }

@@ -44,8 +44,10 @@ struct ProfScope {
 };
 
 // Bit g of the two words: global column g (< n) is not one of `cols`.
+// Wide plans (n > kMaxCols) clear their stack before every pass instead.
 void set_other_cols(uint64_t (&w)[2], int n, const std::vector<int32_t> &cols) {
     w[0] = w[1] = 0;
+    if (n > kMaxCols) return;
     for (int g = 0; g < n; ++g) w[g >> 6] |= 1ull << (g & 63);
     for (int32_t c : cols) w[c >> 6] &= ~(1ull << (c & 63));
 }
@@ -83,7 +85,8 @@ JoinSrc join_src(const figaro_plan_s *p, const RelPlan &Rl, int v, const Buffers
         js.cidx[c] = Rl.d_cidx[c];
         js.mult[c] = Rl.d_mult[c];
     }
-    for (int c = 0; c < Rl.nsub; ++c) js.code[c] = ((int32_t)Rl.col_src[c] + 1) << 8 | (uint8_t)Rl.col_idx[c];
+    for (int c = 0; c < Rl.nsub && c < kMaxCols; ++c)
+        js.code[c] = ((int32_t)Rl.col_src[c] + 1) << 8 | (uint8_t)Rl.col_idx[c];
     return js;
 }
 
@@ -94,6 +97,10 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
                        int64_t *ld_groups, const JoinSrc *js = nullptr) {
     const double *cur = in;
     int64_t ld = ld_in;
+    // the tails of a wide plan's wide heads_and_tails task go to its region,
+    // in the task's own columns
+    const bool region = fuse && T.d_region != nullptr;
+    const bool wide = T.ncols > kFusedMaxCols;
     for (auto &L : T.levels) {
         HelmertArgs a{};
         a.in = cur;
@@ -119,14 +126,14 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
         a.stack_row0 = L.stack_row0;
         a.n_total = p->n;
         set_other_cols(a.other_cols, p->n, T.cols);
-        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint8_t)T.cols[c];
+        if (!wide)
+            for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint16_t)T.cols[c];
         // upper levels of the fused pass write their tail rows into the
         // stack, and so do all levels of a wide task
-        const bool wide = T.ncols > kFusedMaxCols;
         const bool fold = fuse && (&L == &T.levels[0]) && !wide;
         const bool to_stack = fuse && !fold;
-        a.r0 = to_stack ? p->d_stack[0] : r0;
-        a.ld_r0 = to_stack ? p->stack_ld[0] : ld_r0;
+        a.r0 = to_stack ? (region ? T.d_region : p->d_stack[0]) : r0;
+        a.ld_r0 = to_stack ? (region ? T.region_ld : p->stack_ld[0]) : ld_r0;
         a.r0_row0 = to_stack ? L.stack_row0 : L.r0_row0;
         if (fold && !r0) a.r0 = nullptr;
         a.block_of_row = to_stack ? nullptr : block_of_row;
@@ -149,7 +156,7 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
                     ac.join_col0 = c0;
                     ac.ncols = std::min(kChunkCols, T.ncols - c0);
                     ac.pieces_out = L.d_pieces + (int64_t)c0 * L.npieces;
-                    for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint8_t)T.cols[c0 + c];
+                    for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint16_t)(region ? c0 + c : T.cols[c0 + c]);
                     if (c0 > 0) ac.other_cols[0] = ac.other_cols[1] = 0;
                     FIGARO_TRY(launch_helmert(ac, L.unit, false, L.variant, s));
                 }
@@ -163,6 +170,35 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
     return FIGARO_OK;
 }
 
+// Post-processing of a wide plan: the R of every region onto the diagonal
+// of the stack's first n rows, then the QR of the whole stack, whose first
+// n rows are upper triangular (triangular-pentagonal form).
+figaro_status wide_post(figaro_plan_s *p, double *R, hipStream_t s) {
+    const int32_t n = p->n;
+    std::string err;
+    for (int v : p->post) {
+        Task &T = p->rel[v].a2;
+        if (!T.active || !T.d_region) continue;
+        const int64_t h = T.region_ld;
+        {
+            ProfScope ps(p, s, 5, 8.0 * (double)h * T.ncols,
+                         2.0 * (double)h * T.ncols * T.ncols - 2.0 / 3.0 * T.ncols * (double)T.ncols * T.ncols);
+            figaro_status st = wide_qr(p->wqr, T.d_region, T.region_ld, h, T.ncols, false, s, err);
+            if (st != FIGARO_OK) return set_error(p, st, err);
+        }
+        FIGARO_TRY(launch_copy_upper(T.d_region, T.region_ld, h, T.ncols, p->d_stack[0], p->stack_ld[0],
+                                     T.cols[0], T.cols[0], s));
+    }
+    {
+        const double g = (double)(p->stack_rows - n);
+        ProfScope ps(p, s, 5, 8.0 * (double)p->stack_rows * n, 2.0 * g * n * (double)n);
+        figaro_status st = wide_qr(p->wqr, p->d_stack[0], p->stack_ld[0], p->stack_rows, n, true, s, err);
+        if (st != FIGARO_OK) return set_error(p, st, err);
+    }
+    FIGARO_TRY(launch_final_r(p->d_stack[0], p->stack_ld[0], n, n, R, s));
+    return FIGARO_OK;
+}
+
 figaro_status forward(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse, double *R,
                       double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, bool stop_before_tsqr = false,
                       Buffers *keep = nullptr) {
@@ -171,6 +207,11 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
     // pass recomputes them for the backward pass (keep), which reads them
     // again and wants them stored.
     const bool join_in_place = keep == nullptr;
+    if (p->wide && fuse) {
+        // tasks write their columns only: the rest of the stack is zero
+        ProfScope ps(p, s, 5, 8.0 * (double)p->stack_rows * p->n, 0.0);
+        FIGARO_TRY(launch_fill(p->d_stack[0], (int64_t)p->n * p->stack_ld[0], 0.0, s));
+    }
     Buffers B;
     B.own.assign(p->r, nullptr);
     B.ld_own.assign(p->r, 0);
@@ -203,10 +244,8 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
             j.own_pos = Rl.own_pos;
             j.own_mult = Rl.d_own_mult;
             j.nchildren = (int32_t)Rl.children.size();
-            for (int c = 0; c < Rl.nsub; ++c) {
-                j.col_src[c] = Rl.col_src[c];
-                j.col_idx[c] = Rl.col_idx[c];
-            }
+            j.col_src = Rl.d_col_src;
+            j.col_idx = Rl.d_col_idx;
             for (size_t c = 0; c < Rl.children.size(); ++c) {
                 int ch = Rl.children[c];
                 j.sigma[c] = B.sigma[ch];
@@ -263,6 +302,7 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
     }
     if (keep) *keep = B;
     if (!fuse || stop_before_tsqr) return FIGARO_OK;
+    if (p->wide) return wide_post(p, R, s);
     // post-processing TSQR over the stack
     int cur = 0;
     for (size_t d = 0; d < p->dense.size(); ++d) {
@@ -429,6 +469,7 @@ figaro_status run_backward(figaro_plan_s *p, const double *const *values, const 
                            const double *dR, double *const *dvalues, const int64_t *ld_dv, hipStream_t s) {
     figaro_status st = check_inputs(p, values, ld);
     if (st != FIGARO_OK) return st;
+    if (p->wide) return set_error(p, FIGARO_EUNSUPPORTED, "the backward pass handles at most 128 columns");
     for (int i = 0; i < p->r; ++i)
         if (!dvalues[i] || ld_dv[i] < p->rel[i].m)
             return set_error(p, FIGARO_EINVAL, "dvalues[" + std::to_string(i) + "] is NULL or its ld too small");
@@ -446,6 +487,7 @@ figaro_status figaro_r_backward(figaro_plan_t p, const double *const *values, co
     if (!R || !dR || !dvalues || !ld_dvalues) return set_error(p, FIGARO_EINVAL, "NULL argument");
     figaro_status st = check_inputs(p, values, ld);
     if (st != FIGARO_OK) return st;
+    if (p->wide) return set_error(p, FIGARO_EUNSUPPORTED, "the backward pass handles at most 128 columns");
     for (int i = 0; i < p->r; ++i)
         if (!dvalues[i] || ld_dvalues[i] < p->rel[i].m)
             return set_error(p, FIGARO_EINVAL, "dvalues[" + std::to_string(i) + "] is NULL or its ld too small");
@@ -544,7 +586,7 @@ figaro_status figaro_debug_dense_step(int32_t n, int64_t rows, const double *in,
 }
 
 int32_t figaro_debug_stack_layout(figaro_plan_t p, int64_t *out, int32_t max_regions) {
-    if (!p || !out) return -1;
+    if (!p || !out || p->wide) return -1;
     int32_t k = 0;
     for (int v : p->post) {
         RelPlan &R = p->rel[v];
@@ -578,6 +620,7 @@ int32_t figaro_debug_stack_layout(figaro_plan_t p, int64_t *out, int32_t max_reg
 figaro_status figaro_debug_stack(figaro_plan_t p, const double *const *values, const int64_t *ld, double *host_out,
                                  hipStream_t stream) {
     if (!p || !host_out) return set_error(p, FIGARO_EINVAL, "bad argument");
+    if (p->wide) return set_error(p, FIGARO_EUNSUPPORTED, "wide plans reduce their stack in place");
     figaro_status st = check_inputs(p, values, ld);
     if (st != FIGARO_OK) return st;
     st = forward(p, values, ld, true, nullptr, nullptr, 0, nullptr, stream, true);

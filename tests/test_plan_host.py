@@ -119,3 +119,15 @@ def test_config5_sample_covers_every_stratum():
         inst = synth.config5_instance(i)
         p = synth.config5_params(i)
         assert [rel.rows for rel in inst.rels] == p["rows"] and inst.n == p["n"]
+
+
+def test_column_limits():
+    """Plans take up to 16384 data columns in total (above 128 the stack is
+    reduced by the blocked QR); more are refused before any work."""
+    inst = synth.cartesian_uniform(7, 3, 150, 4, 100)
+    p = host_plan(inst)
+    assert p.n == 250
+    wide = synth.cartesian_uniform(8, 2, 16384, 2, 1)
+    with pytest.raises(F.FigaroError) as e:
+        host_plan(wide)
+    assert e.value.name == "EUNSUPPORTED"
