@@ -285,6 +285,79 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
     return out
 
 
+# FiGaRo-MKL seconds for R of the Cartesian product of two m x n relations
+# (experiments section, Exp. 1 synthetic table; a 2x24-core CPU server):
+# rows m -> seconds for n = 64, 256, 1024, 4096 columns per relation.
+PAPER_EXP1_S = {512: (0.10, 0.13, 0.17, 0.43), 1024: (0.10, 0.13, 0.30, 0.81), 2048: (0.12, 0.15, 0.31, 1.77),
+                4096: (0.12, 0.14, 0.38, 4.65), 8192: (0.13, 0.18, 0.54, 5.85)}
+
+
+def wide_grid(F, reps, warmup, cells=None):
+    """The synthetic Cartesian-product grid of Exp. 1: S, T in R^{m x n}
+    with entries uniform in [-3, 3), R of S x T (n <= 64 per relation: the
+    register-tile path; wider: the blocked QR).  Every cell is timed eager
+    and replayed from a captured HIP graph, and checked by the property that
+    holds at any size: R^T R equals the Gram matrix of the product,
+    [m S^T S, s^T t; t^T s, m T^T T] with s, t the column sums."""
+    import torch
+    out = []
+    cols_list = (64, 256, 1024, 4096)
+    if cells is None:
+        cells = [(m, n) for m in sorted(PAPER_EXP1_S) for n in cols_list]
+    for m, n in cells:
+        if True:
+            j = cols_list.index(n) if n in cols_list else -1
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1000003 * m + n)
+            S = torch.rand((n, m), generator=g, dtype=torch.float64, device="cuda") * 6.0 - 3.0
+            T = torch.rand((n, m), generator=g, dtype=torch.float64, device="cuda") * 6.0 - 3.0
+            views = [F._RelView([], torch.zeros((0, m), dtype=torch.int32, device="cuda"), n, -1),
+                     F._RelView([], torch.zeros((0, m), dtype=torch.int32, device="cuda"), n, 0)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan = F.Plan(views)
+            torch.cuda.synchronize()
+            t_plan = time.perf_counter() - t0
+            vals = [plan.to_plan_order(0, S), plan.to_plan_order(1, T)]
+            t_eager, R, _ = time_forward(plan, vals, reps, warmup)
+            gb = F.Batch([plan], streams=1)
+            gs = torch.cuda.Stream()
+            gout = [torch.empty((plan.n, plan.n), dtype=torch.float64, device="cuda")]
+            with torch.cuda.stream(gs):
+                Rg = gb.capture([vals], gout, gs)[0]
+            gs.synchronize()
+            gb.launch(gs)
+            gs.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                gb.launch(gs)
+            gs.synchronize()
+            t_graph = (time.perf_counter() - t0) / reps
+            same = bool(torch.equal(Rg, R))
+            gb.close()
+            # R^T R against the Gram matrix of S x T
+            St, Tt = S.t().contiguous(), T.t().contiguous()
+            G = torch.empty((2 * n, 2 * n), dtype=torch.float64, device="cuda")
+            G[:n, :n] = m * (St.t() @ St)
+            G[n:, n:] = m * (Tt.t() @ Tt)
+            G[:n, n:] = torch.outer(St.sum(0), Tt.sum(0))
+            G[n:, :n] = G[:n, n:].t()
+            Rc = R.contiguous()
+            res = float(torch.linalg.norm(Rc.t() @ Rc - G) / torch.linalg.norm(G))
+            t = min(t_eager, t_graph)
+            cell = {"rows": m, "cols_per_relation": n, "n": 2 * n, "plan_s": t_plan,
+                    "ms_eager": t_eager * 1e3, "ms_graph": t_graph * 1e3, "graph_equals_eager": same,
+                    "join_rows_per_s": m * m / t, "gram_residual": res,
+                    "paper_figaro_mkl_s": PAPER_EXP1_S[m][j] if (m in PAPER_EXP1_S and j >= 0) else None}
+            log(f"wide grid: m={m} n={n} {t * 1e3:.2f} ms gram_residual={res:.2e}")
+            out.append(cell)
+            plan.close()
+            del S, T, St, Tt, G, vals, R, Rg, gout, Rc
+            torch.cuda.empty_cache()
+    return {"workload": "Cartesian product S x T, S and T m x n uniform in [-3, 3) (Exp. 1 synthetic grid)",
+            "cells": out}
+
+
 def batched(F, count, steps, warmup, cache_path=None):
     """The batched workload: instances 0..count-1 (seeds 5000+i), one plan
     each, run as one batch on 8 streams, eager and replayed from a captured
@@ -393,6 +466,11 @@ def main():
                     help="instances of the batched workload (the first N of 512; 0: skip)")
     ap.add_argument("--tuning-cache", default=None,
                     help="JSON file of the autotuner's choice per shape class (read and updated)")
+    ap.add_argument("--no-wide-grid", action="store_true")
+    ap.add_argument("--wide-grid-only", action="store_true",
+                    help="run only the Cartesian-product grid (no headline line)")
+    ap.add_argument("--wide-grid-cells", default=None,
+                    help="comma-separated ROWSxCOLS cells of the grid (default: all 20)")
     ap.add_argument("--cpu-div", type=int, default=100)
     ap.add_argument("--comparator-div", type=int, default=200)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -409,6 +487,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    cells = None
+    if args.wide_grid_cells:
+        cells = [tuple(int(x) for x in c.split("x")) for c in args.wide_grid_cells.split(",")]
+    if args.wide_grid_only:
+        print(json.dumps({"wide_grid": wide_grid(F, 3, 1, cells=cells)}), flush=True)
+        return
     log("generating the two-relation inputs")
     inst = synth.config2()
     plan, t_plan, t_plan_host = plan_times(F, inst)
@@ -481,6 +565,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_star:
         out["star"] = star(F, max(3, args.steps // 2), 2, not args.no_comparator, not args.no_tree_choice)
+    if not args.no_wide_grid:
+        out["wide_grid"] = wide_grid(F, 3, 1, cells=cells)
     if args.batched > 0:
         out["batched"] = batched(F, args.batched, max(3, args.steps // 4), 2, args.tuning_cache)
     if not args.no_comparator:

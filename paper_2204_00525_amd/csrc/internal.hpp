@@ -249,10 +249,20 @@ hipError_t launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 // Blocked Householder QR (wideqr.hip).
 int64_t wide_qr_panel_rows(int64_t h, int32_t n, bool tp);
 int64_t wide_qr_workspace_doubles(int64_t max_nv, int32_t n);
-figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, std::string &err);
+// Workspace carving; blas: a rocBLAS handle to share, or null to create one.
+figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, void *blas, std::string &err);
 void wide_qr_release(WideQr &w);
-figaro_status wide_qr(const WideQr &w, double *A, int64_t lda, int64_t h, int32_t n, bool tp, hipStream_t s,
-                      std::string &err);
+// One QR of the blocked kind: A (h x n, lda) in place, general (tp false)
+// or with rows [0, n) an upper triangular block (tp true).
+struct WideQrJob {
+    const WideQr *w;
+    double *A;
+    int64_t lda, h;
+    int32_t n;
+    bool tp;
+};
+// Independent QRs side by side: their panels share launches.
+figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, std::string &err);
 hipError_t launch_copy_upper(const double *src, int64_t ld_src, int64_t rows, int32_t cols, double *dst,
                              int64_t ld_dst, int64_t row0, int64_t col0, hipStream_t s);
 hipError_t launch_final_r(const double *A, int64_t lda, int64_t rows, int32_t n, double *R, hipStream_t s);
@@ -375,9 +385,11 @@ struct WideQr {
     double *V = nullptr;      // [32][ldv] reflectors of one panel (virtual rows)
     int64_t ldv = 0;
     double *tau = nullptr;    // [n]
-    double *T = nullptr;      // [32][32]
-    double *G = nullptr;      // [32][32]
-    double *W = nullptr;      // [n][32]
+    double *T = nullptr;      // V^T V of the current panel, [32][32]
+    double *G = nullptr;      // partial products V^T V, [parts][32][32]
+    double *W = nullptr;      // T^T V^T C, [n][32]
+    double *Wp = nullptr;     // partial products V^T C, [parts][n][32]
+    int64_t wp_stride = 0;
     double *part = nullptr;   // partial sums of the per-column passes
     double *head = nullptr;
     void *blas = nullptr;     // rocblas_handle
@@ -414,7 +426,8 @@ struct figaro_plan_s {
     // wide heads_and_tails tasks on the diagonal, the other stack rows
     // follow; the whole stack is reduced by the blocked QR
     bool wide = false;
-    figaro::WideQr wqr;
+    figaro::WideQr wqr;                       // the final QR of the stack (owns the rocBLAS handle)
+    std::vector<figaro::WideQr> region_qr;    // one per region, in post order of their relations
     int64_t r0_rows = 0;
     double *d_K = nullptr;           // n x n, backward
     double *d_W = nullptr;           // n x n scratch of the QR adjoint

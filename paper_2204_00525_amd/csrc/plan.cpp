@@ -854,7 +854,7 @@ figaro_status finish_plan(figaro_plan_s *p) {
     // heads_and_tails tasks, whose tails go to regions of their own.
     int64_t srow = p->wide ? n : 0, r0row = 0;
     std::vector<Task *> regions;
-    int64_t region_doubles = 0, max_panel_rows = 0;
+    int64_t region_doubles = 0;
     for (int v : p->post) {
         auto &R = p->rel[v];
         for (Task *T : {&R.a2, &R.a4}) {
@@ -881,7 +881,6 @@ figaro_status finish_plan(figaro_plan_s *p) {
             if (region) {
                 T->region_ld = std::max<int64_t>(rrow, 1);
                 region_doubles += T->region_ld * T->ncols;
-                max_panel_rows = std::max(max_panel_rows, wide_qr_panel_rows(T->region_ld, T->ncols, false));
                 regions.push_back(T);
             }
         }
@@ -895,23 +894,35 @@ figaro_status finish_plan(figaro_plan_s *p) {
     p->stack_rows = srow;
     p->r0_rows = r0row;
     if (p->wide) {
-        max_panel_rows = std::max(max_panel_rows, wide_qr_panel_rows(srow, n, true));
+        // workspaces: the final QR's, then one per region (their panels
+        // share launches, so each keeps its reflectors apart)
+        const int64_t final_rows = wide_qr_panel_rows(srow, n, true);
+        int64_t ws_doubles = wide_qr_workspace_doubles(final_rows, n);
+        for (Task *T : regions)
+            ws_doubles += wide_qr_workspace_doubles(wide_qr_panel_rows(T->region_ld, T->ncols, false), T->ncols);
         p->stack_ld[0] = std::max<int64_t>(srow, 1);
         double *ws = nullptr, *reg = nullptr;
         if (dev_alloc(p, (void **)&p->d_stack[0], sizeof(double) * (size_t)n * (size_t)p->stack_ld[0]) !=
                 hipSuccess ||
             dev_alloc(p, (void **)&reg, sizeof(double) * (size_t)region_doubles) != hipSuccess ||
-            dev_alloc(p, (void **)&ws, sizeof(double) * (size_t)wide_qr_workspace_doubles(max_panel_rows, n)) !=
-                hipSuccess ||
+            dev_alloc(p, (void **)&ws, sizeof(double) * (size_t)ws_doubles) != hipSuccess ||
             dev_alloc(p, (void **)&p->d_status, sizeof(int32_t) * 4) != hipSuccess)
             return set_error(p, FIGARO_ENOMEM, "hipMalloc");
-        for (Task *T : regions) {
+        std::string err;
+        if (figaro_status st = wide_qr_init(p->wqr, ws, final_rows, n, nullptr, err); st != FIGARO_OK)
+            return set_error(p, st, err);
+        ws += wide_qr_workspace_doubles(final_rows, n);
+        p->region_qr.resize(regions.size());
+        for (size_t q = 0; q < regions.size(); ++q) {
+            Task *T = regions[q];
             T->d_region = reg;
             reg += T->region_ld * T->ncols;
+            const int64_t rows = wide_qr_panel_rows(T->region_ld, T->ncols, false);
+            if (figaro_status st = wide_qr_init(p->region_qr[q], ws, rows, T->ncols, p->wqr.blas, err);
+                st != FIGARO_OK)
+                return set_error(p, st, err);
+            ws += wide_qr_workspace_doubles(rows, T->ncols);
         }
-        std::string err;
-        if (figaro_status st = wide_qr_init(p->wqr, ws, max_panel_rows, n, err); st != FIGARO_OK)
-            return set_error(p, st, err);
         return FIGARO_OK;
     }
     // dense TSQR levels over the stack: a workgroup folds tiles_per_wave

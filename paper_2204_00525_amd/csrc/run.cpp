@@ -176,23 +176,32 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
 figaro_status wide_post(figaro_plan_s *p, double *R, hipStream_t s) {
     const int32_t n = p->n;
     std::string err;
+    // the regions side by side (in post order, as their workspaces)
+    std::vector<WideQrJob> jobs;
+    std::vector<Task *> tasks;
+    double flops = 0.0, bytes = 0.0;
     for (int v : p->post) {
         Task &T = p->rel[v].a2;
         if (!T.active || !T.d_region) continue;
-        const int64_t h = T.region_ld;
-        {
-            ProfScope ps(p, s, 5, 8.0 * (double)h * T.ncols,
-                         2.0 * (double)h * T.ncols * T.ncols - 2.0 / 3.0 * T.ncols * (double)T.ncols * T.ncols);
-            figaro_status st = wide_qr(p->wqr, T.d_region, T.region_ld, h, T.ncols, false, s, err);
-            if (st != FIGARO_OK) return set_error(p, st, err);
-        }
-        FIGARO_TRY(launch_copy_upper(T.d_region, T.region_ld, h, T.ncols, p->d_stack[0], p->stack_ld[0],
-                                     T.cols[0], T.cols[0], s));
+        const double h = (double)T.region_ld, c = T.ncols;
+        jobs.push_back({&p->region_qr[tasks.size()], T.d_region, T.region_ld, T.region_ld, T.ncols, false});
+        tasks.push_back(&T);
+        flops += 2.0 * h * c * c - 2.0 / 3.0 * c * c * c;
+        bytes += 8.0 * h * c;
     }
+    if (!jobs.empty()) {
+        ProfScope ps(p, s, 5, bytes, flops);
+        figaro_status st = wide_qr_many(jobs, s, err);
+        if (st != FIGARO_OK) return set_error(p, st, err);
+    }
+    for (Task *T : tasks)
+        FIGARO_TRY(launch_copy_upper(T->d_region, T->region_ld, T->region_ld, T->ncols, p->d_stack[0],
+                                     p->stack_ld[0], T->cols[0], T->cols[0], s));
     {
         const double g = (double)(p->stack_rows - n);
         ProfScope ps(p, s, 5, 8.0 * (double)p->stack_rows * n, 2.0 * g * n * (double)n);
-        figaro_status st = wide_qr(p->wqr, p->d_stack[0], p->stack_ld[0], p->stack_rows, n, true, s, err);
+        figaro_status st =
+            wide_qr_many({{&p->wqr, p->d_stack[0], p->stack_ld[0], p->stack_rows, n, true}}, s, err);
         if (st != FIGARO_OK) return set_error(p, st, err);
     }
     FIGARO_TRY(launch_final_r(p->d_stack[0], p->stack_ld[0], n, n, R, s));

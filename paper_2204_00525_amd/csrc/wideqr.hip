@@ -10,7 +10,8 @@
 //     v = [1; x / (alpha - beta)], beta = -sign(alpha) ||[alpha; x]||,
 //     tau = (beta - alpha) / beta (tau = 0 when x = 0);
 //   * compact WY form of the panel's reflectors, Q = I - V T V^T (T upper
-//     triangular, built column by column from V^T V and tau);
+//     triangular; T is applied through its inverse, diag(1 / tau) plus the
+//     strict upper triangle of V^T V);
 //   * trailing columns C := Q^T C = C - V (T^T (V^T C)), the two products
 //     with V as plain rocBLAS GEMMs.
 //
@@ -65,11 +66,60 @@ struct PanelArgs {
     int64_t rows_per_wg;
 };
 
-// The scalars of one reflector as every workgroup derives them.
+// The panels of up to kMaxJobs independent QRs, factored by one launch:
+// job j owns workgroups [wg0[j], wg0[j + 1]).
+constexpr int kMaxJobs = 8;
+struct PanelBatch {
+    PanelArgs a[kMaxJobs];
+    int32_t wg0[kMaxJobs + 1];
+    int32_t count;
+};
+
+__device__ __forceinline__ int job_of(const PanelBatch &b, int wg) {
+    int j = 0;
+    while (j + 1 < b.count && wg >= b.wg0[j + 1]) ++j;
+    return j;
+}
+
+// The scalars of one reflector, derived by every thread from the
+// reflector's own row and the reduced sums over its tail, both relative to
+// the reflector's column (head[0] = alpha, head[c] = its row in column
+// q + c; tot[0] = ||x||^2, tot[c] = x^T a_{q+c}); w_c = v^T a_{q+c} is read
+// as head[c] + scale * tot[c] where it is used.
 struct Refl {
     double tau, scale, beta;
-    double w[kNb];   // w_c = v^T a_c for the panel's later columns c
+    const double *head, *tot;
 };
+
+__device__ __forceinline__ Refl make_reflector(const double *head, const double *tot) {
+    Refl r;
+    const double alpha = head[0], sig2 = tot[0];
+    r.tau = 0.0;
+    r.scale = 0.0;
+    r.beta = alpha;
+    if (sig2 > 0.0) {
+        r.beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
+        r.tau = (r.beta - alpha) / r.beta;
+        r.scale = 1.0 / (alpha - r.beta);
+    }
+    r.head = head;
+    r.tot = tot;
+    return r;
+}
+
+// Workgroup barrier for LDS traffic only.  The panel kernels' global
+// stores (reflectors, finished columns) are read by later launches alone,
+// so the barrier waits for the LDS operations of every wave and lets the
+// stores drain in the background (a full __syncthreads would wait for
+// them at every column).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// v where keep holds, else +0.  A bit mask rather than a branch, so a
+// load feeding it stays unconditional and all of a row's loads are in
+// flight together (a guarded load compiles to a branch and a wait each).
+__device__ __forceinline__ double keep_or_zero(double v, bool keep) {
+    return __longlong_as_double(__double_as_longlong(v) & -(long long)keep);
+}
 
 __device__ __forceinline__ int64_t real_row(const PanelArgs &a, int64_t t) {
     return t < a.kb ? a.k + t : a.s0 + (t - a.kb);
@@ -81,207 +131,247 @@ __device__ __forceinline__ bool in_tail(const PanelArgs &a, int64_t t, int q) {
     return t > q && (!a.tp || t >= a.kb);
 }
 
-// Reflector q from its row (head[c], c >= q) and the reduced sums over its
-// tail: tot[q] = ||x||^2, tot[c] = x^T a_c for c > q.  Run by thread 0.
-__device__ void make_reflector(const PanelArgs &a, int q, const double *head, const double *tot, Refl &r) {
-    const double alpha = head[q], sig2 = tot[q];
-    double tau = 0.0, scale = 0.0, beta = alpha;
-    if (sig2 > 0.0) {
-        beta = -copysign(sqrt(alpha * alpha + sig2), alpha);
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-    }
-    r.tau = tau;
-    r.scale = scale;
-    r.beta = beta;
-    for (int c = q + 1; c < a.kb; ++c) r.w[c] = head[c] + scale * tot[c];
+// A row held relative to the current column: y[c] is the row's entry in
+// column q + c of the panel, so the pivot is always y[0] and every
+// register index is a compile-time constant.  Entries beyond the panel's
+// live width are zero, in the rows and in the reflector's row and sums, so
+// the loops below run over all kNb entries without a branch.
+//
+// w[c] = v^T a_{q+c}, the same for every row: taken once per step.
+__device__ __forceinline__ void reflector_w(const Refl &r, double (&w)[kNb]) {
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) w[c] = r.head[c] + r.scale * r.tot[c];
 }
 
-// One column step on virtual rows [t0, t1) of a workgroup: apply reflector
-// q = p - 1 (p > 0) with the scalars in r, write column q of V, then add
-// this workgroup's sums for reflector p (p < kb) into acc and keep row p's
-// values in head_out.
-__device__ __forceinline__ void column_step(const PanelArgs &a, int p, int64_t t0, int64_t t1, const Refl &r,
-                                            double (&acc)[kNb], double *head_out) {
-    const int q = p - 1;
-    const int c_lo = p > 0 ? q : p;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += kPassThreads) {
-        double *base = a.A + real_row(a, t) + a.k * a.lda;
-        double x[kNb];
+// Reflector q applied to virtual row t; returns the row's entry of v (1 on
+// the reflector's own row, 0 outside its rows) and whether the row changed.
+__device__ __forceinline__ double apply_row(const PanelArgs &a, int64_t t, int q, const Refl &r,
+                                            const double (&w)[kNb], double (&y)[kNb], bool &changed) {
+    const bool own = t == q, tail = in_tail(a, t, q);
+    const double v = own ? 1.0 : (tail ? y[0] * r.scale : 0.0);
+    const double f = own ? r.tau : r.tau * v;
+    y[0] = own ? r.beta : (tail ? v : y[0]);
+#pragma unroll
+    for (int c = 1; c < kNb; ++c) y[c] -= f * w[c];
+    changed = own || tail;
+    return v;
+}
+
+// Drop the pivot column: y[c] = y[c + 1].
+__device__ __forceinline__ void shift_row(double (&y)[kNb]) {
+#pragma unroll
+    for (int c = 0; c + 1 < kNb; ++c) y[c] = y[c + 1];
+    y[kNb - 1] = 0.0;
+}
+
+// Row t's share of the sums of reflector p (y relative to column p):
+// ||x||^2 and x^T a_{p+c} into acc[c] for its tail rows; its own row goes
+// to head_out.
+__device__ __forceinline__ void accumulate_row(const PanelArgs &a, int64_t t, int p, const double (&y)[kNb],
+                                               double (&acc)[kNb], double *head_out) {
+    if (t == p) {
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) head_out[c] = y[c];
+    }
+    const double y0 = in_tail(a, t, p) ? y[0] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) acc[c] += y0 * y[c];
+}
+
+// Sum acc[c] over the workgroup of TH threads into out[c] (all kNb
+// entries): every thread's values through LDS (buf, column-major by
+// thread), then TH / 32 threads per column add 32 each and combine within
+// their group of lanes.  Ends with the values in out visible to the thread
+// that wrote them only; the caller synchronises before others read them.
+// (Rows of buf are TH + 1 doubles long, so the 32 columns a wave reads at
+// once fall in different LDS banks.)
+template <int TH>
+__device__ __forceinline__ void block_sum(const double (&acc)[kNb], double (*buf)[TH + 1], double *out) {
+    constexpr int SEG = TH / kNb;
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) buf[c][threadIdx.x] = acc[c];
+    lds_barrier();
+    const int c = threadIdx.x / SEG, sg = threadIdx.x % SEG;
+    double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNb; k += 2) {
+        v0 += buf[c][k * SEG + sg];
+        v1 += buf[c][(k + 1) * SEG + sg];
+    }
+    double v = v0 + v1;
+#pragma unroll
+    for (int off = 1; off < SEG; off <<= 1) v += __shfl_xor(v, off);
+    if (sg == 0) out[c] = v;
+}
+
+template <int TH>
+struct OneShared {
+    double buf[kNb][TH + 1];
+    double tot[2][kNb], head[2][kNb];
+};
+
+// Whole panel in one workgroup of TH threads (nv <= RPT * TH): thread i
+// holds virtual rows i, i + TH, ... in registers, relative to the current
+// column; a column leaves the registers for memory when it has been the
+// pivot.  The sums and the reflector's row alternate between two LDS
+// buffers by column parity.
+template <int RPT, int TH>
+__global__ __launch_bounds__(TH) void k_panel_one(PanelBatch batch) {
+    __shared__ OneShared<TH> sh;
+    const PanelArgs a = batch.a[blockIdx.x];
+    double y[RPT][kNb];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int64_t t = threadIdx.x + (int64_t)i * TH;
+        const double *base = a.A + real_row(a, t < a.nv ? t : 0) + a.k * a.lda;
 #pragma unroll
         for (int c = 0; c < kNb; ++c)
-            if (c >= c_lo && c < a.kb) x[c] = base[c * a.lda];
-        if (p > 0) {
-            double v;
-            bool changed = true;
-            if (t == q) {
-                v = 1.0;
-                x[q] = r.beta;
-#pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c > q && c < a.kb) x[c] -= r.tau * r.w[c];
-            } else if (in_tail(a, t, q)) {
-                v = x[q] * r.scale;
-                x[q] = v;
-                const double tv = r.tau * v;
-#pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c > q && c < a.kb) x[c] -= tv * r.w[c];
-            } else {
-                v = 0.0;
-                changed = false;
-            }
-            a.V[(int64_t)q * a.ldv + t] = v;
-            if (changed) {
-#pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c >= q && c < a.kb) base[c * a.lda] = x[c];
-            }
-        }
-        if (p < a.kb) {
-            if (t == p) {
-#pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c >= p && c < a.kb) head_out[c] = x[c];
-            } else if (in_tail(a, t, p)) {
-                const double xp = x[p];
-#pragma unroll
-                for (int c = 0; c < kNb; ++c)
-                    if (c >= p && c < a.kb) acc[c] += xp * x[c];
-            }
-        }
+            y[i][c] = keep_or_zero(base[(int64_t)(c < a.kb ? c : a.kb - 1) * a.lda], t < a.nv && c < a.kb);
     }
-}
-
-// Sum acc[c] (c in [p, kb)) over the workgroup into out[c] (LDS scratch red).
-__device__ void block_sum(const PanelArgs &a, int p, double (&acc)[kNb], double (*red)[kPassThreads / 64],
-                          double *out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < kNb; ++c) {
-        if (c < p || c >= a.kb) continue;
-        double v = acc[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[c][wave] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x >= p && threadIdx.x < a.kb) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kPassThreads / 64; ++w) s += red[threadIdx.x][w];
-        out[threadIdx.x] = s;
-    }
-}
-
-// Whole panel in one workgroup (nv <= kSmallRows).
-__global__ __launch_bounds__(kPassThreads) void k_panel_one(PanelArgs a) {
-    __shared__ double red[kNb][kPassThreads / 64];
-    __shared__ double tot[kNb], head[kNb];
-    __shared__ Refl r;
     for (int p = 0; p <= a.kb; ++p) {
+        Refl r{};
+        double w[kNb];
         if (p > 0) {
-            if (threadIdx.x == 0) {
-                make_reflector(a, p - 1, head, tot, r);
-                a.tau[p - 1] = r.tau;
-            }
-            __syncthreads();
+            r = make_reflector(sh.head[(p - 1) & 1], sh.tot[(p - 1) & 1]);
+            reflector_w(r, w);
+            if (threadIdx.x == 0) a.tau[p - 1] = r.tau;
         }
         double acc[kNb];
 #pragma unroll
         for (int c = 0; c < kNb; ++c) acc[c] = 0.0;
-        __shared__ double head_next[kNb];
-        column_step(a, p, 0, a.nv, r, acc, head_next);
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int64_t t = threadIdx.x + (int64_t)i * TH;
+            if (t >= a.nv) continue;
+            if (p > 0) {
+                bool changed;
+                a.V[(int64_t)(p - 1) * a.ldv + t] = apply_row(a, t, p - 1, r, w, y[i], changed);
+                a.A[real_row(a, t) + (a.k + p - 1) * a.lda] = y[i][0];
+                shift_row(y[i]);
+            }
+            accumulate_row(a, t, p, y[i], acc, sh.head[p & 1]);
+        }
         if (p < a.kb) {
-            block_sum(a, p, acc, red, tot);
-            __syncthreads();
-            if (threadIdx.x < kNb) head[threadIdx.x] = head_next[threadIdx.x];
-            __syncthreads();
+            block_sum<TH>(acc, sh.buf, sh.tot[p & 1]);
+            lds_barrier();
         }
     }
 }
 
-// One column step of a tall panel; workgroup b owns virtual rows
+// Column step p of a tall panel; workgroup b owns virtual rows
 // [b * rows_per_wg, (b + 1) * rows_per_wg).  Partial sums and the
 // reflector's row alternate between two buffers by column parity, so a
 // launch never overwrites what a workgroup of the same launch still reads.
-__global__ __launch_bounds__(kPassThreads) void k_panel_pass(PanelArgs a, int p) {
-    __shared__ double red[kNb][kPassThreads / 64];
+__global__ __launch_bounds__(kPassThreads) void k_panel_pass(PanelBatch batch, int p) {
+    __shared__ double buf[kNb][kPassThreads + 1];
     __shared__ double tot[kNb], hd[kNb];
-    __shared__ Refl r;
+    const int job = job_of(batch, blockIdx.x);
+    const PanelArgs a = batch.a[job];
+    const int wg = blockIdx.x - batch.wg0[job];
+    if (p > a.kb) return;   // a narrower panel of the batch is done
+    const int q = p - 1;
+    Refl r{};
+    double w[kNb];
     if (p > 0) {
-        const int q = p - 1;
+        // the previous launch's partial sums: 8 threads per column
         const double *prt = a.part + (int64_t)(q & 1) * a.wgs * kPartStride;
-        const double *hq = a.head + (q & 1) * kPartStride;
-        const int c = threadIdx.x;
-        if (c >= q && c < a.kb) {
-            double s = 0.0;
-            for (int b = 0; b < a.wgs; ++b) s += prt[(int64_t)b * kPartStride + c];
-            tot[c] = s;
-            hd[c] = hq[c];
+        const int c = threadIdx.x >> 3, sg = threadIdx.x & 7;
+        double v = 0.0;
+        for (int b = sg; b < a.wgs; b += 8) v += prt[(int64_t)b * kPartStride + c];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        if (sg == 0) {
+            tot[c] = v;
+            hd[c] = a.head[(q & 1) * kPartStride + c];
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            make_reflector(a, q, hd, tot, r);
-            if (blockIdx.x == 0) a.tau[q] = r.tau;
-        }
-        __syncthreads();
+        lds_barrier();
+        r = make_reflector(hd, tot);
+        reflector_w(r, w);
+        if (wg == 0 && threadIdx.x == 0) a.tau[q] = r.tau;
     }
-    const int64_t t0 = (int64_t)blockIdx.x * a.rows_per_wg;
+    const int c_lo = p > 0 ? q : p;
+    const int width = a.kb - c_lo;
+    const int64_t t0 = (int64_t)wg * a.rows_per_wg;
     const int64_t t1 = std::min<int64_t>(a.nv, t0 + a.rows_per_wg);
     double acc[kNb];
 #pragma unroll
     for (int c = 0; c < kNb; ++c) acc[c] = 0.0;
-    column_step(a, p, t0, t1, r, acc, a.head + (p & 1) * kPartStride);
-    if (p < a.kb) {
-        __syncthreads();
-        block_sum(a, p, acc, red, a.part + ((int64_t)(p & 1) * a.wgs + blockIdx.x) * kPartStride);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += kPassThreads) {
+        double *base = a.A + real_row(a, t) + (a.k + c_lo) * a.lda;
+        double y[kNb];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[c] = keep_or_zero(base[(int64_t)(c < width ? c : width - 1) * a.lda], c < width);
+        if (p > 0) {
+            bool changed;
+            a.V[(int64_t)q * a.ldv + t] = apply_row(a, t, q, r, w, y, changed);
+            if (changed) {
+                // highest column first: the clamped addresses of the
+                // columns beyond the width all land on the last live
+                // column, which its own store then sets
+#pragma unroll
+                for (int c = kNb - 1; c >= 0; --c)
+                    base[(int64_t)(c < width ? c : width - 1) * a.lda] = c < width ? y[c] : 0.0;
+            }
+            shift_row(y);
+        }
+        if (p < a.kb) accumulate_row(a, t, p, y, acc, a.head + (p & 1) * kPartStride);
+    }
+    if (p < a.kb) block_sum<kPassThreads>(acc, buf, a.part + ((int64_t)(p & 1) * a.wgs + wg) * kPartStride);
+}
+
+// G = V^T V from its nparts partial products (part b at Gp + b * kNb * kNb).
+__global__ __launch_bounds__(256) void k_wy_g(const double *Gp, int nparts, double *G) {
+    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        int b = 0;
+        for (; b + 4 <= nparts; b += 4) {
+            g0 += Gp[(int64_t)(b + 0) * kNb * kNb + e];
+            g1 += Gp[(int64_t)(b + 1) * kNb * kNb + e];
+            g2 += Gp[(int64_t)(b + 2) * kNb * kNb + e];
+            g3 += Gp[(int64_t)(b + 3) * kNb * kNb + e];
+        }
+        for (; b < nparts; ++b) g0 += Gp[(int64_t)b * kNb * kNb + e];
+        G[e] = (g0 + g1) + (g2 + g3);
     }
 }
 
-// T of the compact WY form from G = V^T V and tau (one wave):
-//   T[p][p] = tau_p,  T[0:p][p] = -tau_p T[0:p][0:p] G[0:p][p].
-__global__ __launch_bounds__(64) void k_wy_t(const double *G, const double *tau, int kb, double *T) {
-    __shared__ double sT[kNb][kNb + 1];
-    const int i = threadIdx.x;
-    if (i < kNb)
-        for (int j = 0; j < kNb; ++j) sT[i][j] = 0.0;
-    __syncthreads();
-    for (int p = 0; p < kb; ++p) {
-        const double tp = tau[p];
-        double y = 0.0;
-        if (i < p)
-            for (int j = i; j < p; ++j) y += sT[i][j] * G[p * kNb + j];
-        __syncthreads();
-        if (i < p) sT[i][p] = -tp * y;
-        if (i == p) sT[p][p] = tp;
-        __syncthreads();
+// W2 = T^T W for the kb x nc block W, W the sum of nparts partial products
+// (part b at Wp + b * part_stride, kNb x nc, leading dimension kNb), where
+// T is the triangular factor of the compact WY form.  T is never formed:
+// its inverse is diag(1 / tau) + the strict upper triangle of V^T V (the
+// column recurrence of T, inverted block by block), so W2 solves
+// (diag(1 / tau) + strictly-lower(G^T)) W2 = W by forward substitution:
+//   W2_i = tau_i (W_i - sum_{j < i} G(j, i) W2_j),
+// which also gives W2_i = 0 for a reflector with tau_i = 0 (the identity).
+// 32 threads per column, 8 columns per workgroup.
+__global__ __launch_bounds__(256) void k_wy_tw(const double *Wp, int64_t part_stride, int nparts, const double *G,
+                                               const double *tau, int kb, double *W2, int64_t nc) {
+    __shared__ double sG[kNb][kNb + 1];   // sG[q][i] = G(i, q), rows padded against bank conflicts
+    __shared__ double sW[8][kNb];
+    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) sG[e / kNb][e % kNb] = G[e];
+    const int q = threadIdx.x & (kNb - 1), cl = threadIdx.x / kNb;
+    const int64_t c = (int64_t)blockIdx.x * 8 + cl;
+    double w0 = 0.0, w1 = 0.0;
+    if (c < nc && q < kb) {
+        int b = 0;
+        for (; b + 2 <= nparts; b += 2) {
+            w0 += Wp[(int64_t)b * part_stride + c * kNb + q];
+            w1 += Wp[(int64_t)(b + 1) * part_stride + c * kNb + q];
+        }
+        if (b < nparts) w0 += Wp[(int64_t)b * part_stride + c * kNb + q];
     }
-    if (i < kNb)
-        for (int j = 0; j < kNb; ++j) T[j * kNb + i] = sT[i][j];
-}
-
-// W := T^T W for the kb x nc block W (leading dimension kNb), one column per
-// thread.
-__global__ __launch_bounds__(256) void k_wy_tw(const double *T, int kb, double *W, int64_t nc) {
-    __shared__ double sT[kNb * kNb];
-    for (int i = threadIdx.x; i < kNb * kNb; i += blockDim.x) sT[i] = T[i];
+    const double w = w0 + w1;
+    const double tq = q < kb ? tau[q] : 0.0;
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    double w[kNb], o[kNb];
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) w[q] = q < kb ? W[c * kNb + q] : 0.0;
-#pragma unroll
-    for (int p = 0; p < kNb; ++p) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q <= p; ++q) s += sT[p * kNb + q] * w[q];
-        o[p] = s;
+    // step i: thread q == i finishes W2_i (the sum over j < i is complete)
+    double acc = 0.0;
+    for (int i = 0; i < kb; ++i) {
+        if (q == i) sW[cl][i] = tq * (w - acc);
+        __syncthreads();
+        if (q > i) acc += sG[q][i] * sW[cl][i];   // G(i, q) W2_i
     }
-#pragma unroll
-    for (int p = 0; p < kNb; ++p)
-        if (p < kb) W[c * kNb + p] = o[p];
+    if (c < nc && q < kb) W2[c * kNb + q] = sW[cl][q];
 }
 
 // Upper-triangular part of the first min(rows, cols) rows of src (cols
@@ -319,6 +409,39 @@ bool gemm(rocblas_handle h, bool ta, int64_t m, int64_t n, int64_t k, double alp
                          (rocblas_int)ldb, &beta, C, (rocblas_int)ldc) == rocblas_status_success;
 }
 
+// Rows of one slice of the split products V^T X: the long dimension is cut
+// into slices of kSplitRows rows, each a GEMM of its own (one strided
+// batch), and the partial products are summed by the kernel that reads them.
+constexpr int64_t kSplitRows = 512;
+
+int64_t split_parts(int64_t rows) { return std::max<int64_t>(1, (rows + kSplitRows - 1) / kSplitRows); }
+
+// Partial products P_b = V_b^T X_b (kNb x nc each, leading dimension kNb,
+// part b at P + b * part_stride) over the row slices of V (rows x kb, ldv)
+// and X (rows x nc, ldx), from part `first` on.  Returns the parts written.
+bool split_vt_x(rocblas_handle h, int kb, int64_t nc, int64_t rows, const double *V, int64_t ldv, const double *X,
+                int64_t ldx, double *P, int64_t part_stride, int64_t first, int64_t &parts) {
+    parts = 0;
+    if (rows <= 0 || nc <= 0) return true;
+    const int64_t full = rows / kSplitRows, rem = rows - full * kSplitRows;
+    const double one = 1.0, zero = 0.0;
+    if (full > 0) {
+        if (rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, kb, (rocblas_int)nc,
+                                          (rocblas_int)kSplitRows, &one, V, (rocblas_int)ldv, kSplitRows, X,
+                                          (rocblas_int)ldx, kSplitRows, &zero, P + first * part_stride, kNb,
+                                          part_stride, (rocblas_int)full) != rocblas_status_success)
+            return false;
+        parts += full;
+    }
+    if (rem > 0) {
+        if (!gemm(h, true, kb, nc, rem, 1.0, V + full * kSplitRows, ldv, X + full * kSplitRows, ldx, 0.0,
+                  P + (first + parts) * part_stride, kNb))
+            return false;
+        parts += 1;
+    }
+    return true;
+}
+
 }  // namespace
 
 int64_t wide_qr_panel_rows(int64_t h, int32_t n, bool tp) {
@@ -326,22 +449,32 @@ int64_t wide_qr_panel_rows(int64_t h, int32_t n, bool tp) {
 }
 
 int64_t wide_qr_workspace_doubles(int64_t max_nv, int32_t n) {
-    return (int64_t)kNb * max_nv          // V
-           + n                            // tau
-           + 2 * kNb * kNb                // T, G
-           + (int64_t)kNb * n             // W
+    const int64_t parts = split_parts(max_nv) + 1;
+    return (int64_t)kNb * max_nv                          // V
+           + n                                            // tau
+           + kNb * kNb                                    // T
+           + parts * kNb * kNb                            // partial V^T V
+           + (int64_t)kNb * n                             // W2
+           + parts * kNb * std::max<int64_t>(n, kNb)      // partial V^T C
            + 2 * kMaxPassWgs * kPartStride + 2 * kPartStride;
 }
 
-figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, std::string &err) {
+figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, void *blas, std::string &err) {
     w.ldv = std::max<int64_t>(max_nv, 1);
+    const int64_t parts = split_parts(w.ldv) + 1;
     w.V = ws;
     w.tau = w.V + kNb * w.ldv;
     w.T = w.tau + n;
     w.G = w.T + kNb * kNb;
-    w.W = w.G + kNb * kNb;
-    w.part = w.W + (int64_t)kNb * n;
+    w.W = w.G + parts * kNb * kNb;
+    w.Wp = w.W + (int64_t)kNb * n;
+    w.wp_stride = kNb * std::max<int64_t>(n, kNb);
+    w.part = w.Wp + parts * w.wp_stride;
     w.head = w.part + 2 * kMaxPassWgs * kPartStride;
+    if (blas) {   // a handle shared with another workspace of the plan
+        w.blas = blas;
+        return FIGARO_OK;
+    }
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) {
         err = "rocblas_create_handle failed";
@@ -362,16 +495,96 @@ void wide_qr_release(WideQr &w) {
     w.blas = nullptr;
 }
 
-figaro_status wide_qr(const WideQr &w, double *A, int64_t lda, int64_t h, int32_t n, bool tp, hipStream_t s,
-                      std::string &err) {
-    rocblas_handle bh = (rocblas_handle)w.blas;
-    if (!bh || h < (tp ? n : 1) || wide_qr_panel_rows(h, n, tp) > w.ldv) {
-        err = "blocked QR: bad shape";
-        return FIGARO_EINVAL;
+namespace {
+
+// The panel of job J at column k (false once the job has no panel there).
+bool panel_args(const WideQrJob &J, int64_t k, PanelArgs &a) {
+    const int64_t kend = J.tp ? J.n : std::min<int64_t>(J.n, J.h);
+    if (k >= kend) return false;
+    a = PanelArgs{};
+    a.A = J.A;
+    a.lda = J.lda;
+    a.k = k;
+    a.kb = (int32_t)std::min<int64_t>(kNb, kend - k);
+    a.s0 = J.tp ? J.n : k + a.kb;
+    a.tp = J.tp ? 1 : 0;
+    a.nv = a.kb + (J.h - a.s0);
+    a.V = J.w->V;
+    a.ldv = J.w->ldv;
+    a.tau = J.w->tau + k;
+    a.part = J.w->part;
+    a.head = J.w->head;
+    if (a.nv <= kSmallRows) {
+        a.wgs = 1;
+        a.rows_per_wg = a.nv;
+    } else {
+        a.wgs = (int32_t)std::min<int64_t>(kMaxPassWgs, (a.nv + kPassThreads - 1) / kPassThreads);
+        a.rows_per_wg = (a.nv + a.wgs - 1) / a.wgs;
     }
-    if (lda > INT32_MAX || w.ldv > INT32_MAX) {   // rocBLAS takes 32-bit leading dimensions
-        err = "blocked QR: more than 2^31 rows";
-        return FIGARO_EUNSUPPORTED;
+    return true;
+}
+
+// One-workgroup panels: one launch per register shape, one workgroup per job.
+hipError_t launch_small_panels(const std::vector<PanelArgs> &pa, hipStream_t s) {
+    for (int shape = 0; shape < 4; ++shape) {
+        PanelBatch b{};
+        for (const PanelArgs &a : pa) {
+            const int sh = a.nv <= 64 ? 0 : a.nv <= kPassThreads ? 1 : a.nv <= 2 * kPassThreads ? 2 : 3;
+            if (sh == shape) b.a[b.count++] = a;
+        }
+        if (b.count == 0) continue;
+        switch (shape) {
+            case 0: hipLaunchKernelGGL((k_panel_one<1, 64>), dim3(b.count), dim3(64), 0, s, b); break;
+            case 1: hipLaunchKernelGGL((k_panel_one<1, kPassThreads>), dim3(b.count), dim3(kPassThreads), 0, s, b); break;
+            case 2: hipLaunchKernelGGL((k_panel_one<2, kPassThreads>), dim3(b.count), dim3(kPassThreads), 0, s, b); break;
+            default: hipLaunchKernelGGL((k_panel_one<4, kPassThreads>), dim3(b.count), dim3(kPassThreads), 0, s, b);
+        }
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    return hipSuccess;
+}
+
+// Tall panels: one launch per column over the workgroups of every job.
+hipError_t launch_tall_panels(const std::vector<PanelArgs> &pa, hipStream_t s) {
+    if (pa.empty()) return hipSuccess;
+    PanelBatch b{};
+    int kbmax = 0;
+    for (const PanelArgs &a : pa) {
+        b.a[b.count] = a;
+        b.wg0[b.count + 1] = b.wg0[b.count] + a.wgs;
+        ++b.count;
+        kbmax = std::max(kbmax, (int)a.kb);
+    }
+    for (int p = 0; p <= kbmax; ++p) {
+        hipLaunchKernelGGL(k_panel_pass, dim3(b.wg0[b.count]), dim3(kPassThreads), 0, s, b, p);
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, std::string &err) {
+    if (jobs.empty()) return FIGARO_OK;
+    if (jobs.size() > (size_t)kMaxJobs) {
+        for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxJobs) {
+            std::vector<WideQrJob> part(jobs.begin() + j0, jobs.begin() + std::min(jobs.size(), j0 + kMaxJobs));
+            if (figaro_status st = wide_qr_many(part, s, err); st != FIGARO_OK) return st;
+        }
+        return FIGARO_OK;
+    }
+    rocblas_handle bh = (rocblas_handle)jobs[0].w->blas;
+    int64_t kmax = 0;
+    for (const WideQrJob &J : jobs) {
+        if (!J.w->blas || J.h < (J.tp ? J.n : 1) || wide_qr_panel_rows(J.h, J.n, J.tp) > J.w->ldv) {
+            err = "blocked QR: bad shape";
+            return FIGARO_EINVAL;
+        }
+        if (J.lda > INT32_MAX || J.w->ldv > INT32_MAX) {   // rocBLAS takes 32-bit leading dimensions
+            err = "blocked QR: more than 2^31 rows";
+            return FIGARO_EUNSUPPORTED;
+        }
+        kmax = std::max<int64_t>(kmax, J.tp ? J.n : std::min<int64_t>(J.n, J.h));
     }
     if (rocblas_set_stream(bh, s) != rocblas_status_success) {
         err = "rocblas_set_stream failed";
@@ -385,58 +598,57 @@ figaro_status wide_qr(const WideQr &w, double *A, int64_t lda, int64_t h, int32_
         err = "rocblas_dgemm failed";
         return FIGARO_EHIP;
     };
-    const int64_t kend = tp ? n : std::min<int64_t>(n, h);
-    for (int64_t k = 0; k < kend; k += kNb) {
-        PanelArgs a{};
-        a.A = A;
-        a.lda = lda;
-        a.k = k;
-        a.kb = (int32_t)std::min<int64_t>(kNb, kend - k);
-        a.s0 = tp ? n : k + a.kb;
-        a.tp = tp ? 1 : 0;
-        a.nv = a.kb + (h - a.s0);
-        a.V = w.V;
-        a.ldv = w.ldv;
-        a.tau = w.tau + k;
-        a.part = w.part;
-        a.head = w.head;
-        if (a.nv <= kSmallRows) {
-            a.wgs = 1;
-            a.rows_per_wg = a.nv;
-            hipLaunchKernelGGL(k_panel_one, dim3(1), dim3(kPassThreads), 0, s, a);
-            if (hipGetLastError() != hipSuccess) return hip_fail("panel");
-        } else {
-            a.wgs = (int32_t)std::min<int64_t>(kMaxPassWgs, (a.nv + kPassThreads - 1) / kPassThreads);
-            a.rows_per_wg = (a.nv + a.wgs - 1) / a.wgs;
-            for (int p = 0; p <= a.kb; ++p) {
-                hipLaunchKernelGGL(k_panel_pass, dim3(a.wgs), dim3(kPassThreads), 0, s, a, p);
-                if (hipGetLastError() != hipSuccess) return hip_fail("panel pass");
+    for (int64_t k = 0; k < kmax; k += kNb) {
+        std::vector<PanelArgs> small, tall;
+        std::vector<std::pair<const WideQrJob *, PanelArgs>> active;
+        for (const WideQrJob &J : jobs) {
+            PanelArgs a;
+            if (!panel_args(J, k, a)) continue;
+            (a.nv <= kSmallRows ? small : tall).push_back(a);
+            active.push_back({&J, a});
+        }
+        if (launch_small_panels(small, s) != hipSuccess) return hip_fail("panel");
+        if (launch_tall_panels(tall, s) != hipSuccess) return hip_fail("panel pass");
+        for (auto &[Jp, a] : active) {
+            const WideQrJob &J = *Jp;
+            const WideQr &w = *J.w;
+            const int64_t n = J.n, h = J.h, lda = J.lda;
+            const bool tp = J.tp;
+            const int64_t nc = n - k - a.kb;
+            if (nc <= 0) continue;
+            double *C = J.A + (k + a.kb) * lda;   // trailing columns, row 0
+            // V^T V (split over the rows and summed)
+            int64_t gparts = 0;
+            if (!split_vt_x(bh, a.kb, a.kb, a.nv, w.V, w.ldv, w.V, w.ldv, w.G, kNb * kNb, 0, gparts))
+                return blas_fail();
+            hipLaunchKernelGGL(k_wy_g, dim3(1), dim3(256), 0, s, w.G, (int)gparts, w.T);
+            if (hipGetLastError() != hipSuccess) return hip_fail("wy G");
+            // W2 = T^T V^T C over the panel's rows and the tail rows (split
+            // products, summed with the T^T product)
+            int64_t wparts = 0, more = 0;
+            if (!tp) {
+                if (!split_vt_x(bh, a.kb, nc, a.nv, w.V, w.ldv, C + k, lda, w.Wp, w.wp_stride, 0, wparts))
+                    return blas_fail();
+            } else {
+                if (!split_vt_x(bh, a.kb, nc, a.kb, w.V, w.ldv, C + k, lda, w.Wp, w.wp_stride, 0, wparts))
+                    return blas_fail();
+                if (!split_vt_x(bh, a.kb, nc, h - n, w.V + a.kb, w.ldv, C + n, lda, w.Wp, w.wp_stride, wparts, more))
+                    return blas_fail();
+                wparts += more;
             }
-        }
-        const int64_t nc = n - k - a.kb;
-        if (nc <= 0) continue;
-        double *C = A + (k + a.kb) * lda;   // trailing columns, row 0
-        // T from V^T V
-        if (!gemm(bh, true, a.kb, a.kb, a.nv, 1.0, w.V, w.ldv, w.V, w.ldv, 0.0, w.G, kNb)) return blas_fail();
-        hipLaunchKernelGGL(k_wy_t, dim3(1), dim3(64), 0, s, w.G, a.tau, a.kb, w.T);
-        if (hipGetLastError() != hipSuccess) return hip_fail("wy T");
-        // W = V^T C over the panel's rows, then the tail rows
-        if (!tp) {
-            if (!gemm(bh, true, a.kb, nc, a.nv, 1.0, w.V, w.ldv, C + k, lda, 0.0, w.W, kNb)) return blas_fail();
-        } else {
-            if (!gemm(bh, true, a.kb, nc, a.kb, 1.0, w.V, w.ldv, C + k, lda, 0.0, w.W, kNb)) return blas_fail();
-            if (!gemm(bh, true, a.kb, nc, h - n, 1.0, w.V + a.kb, w.ldv, C + n, lda, 1.0, w.W, kNb))
-                return blas_fail();
-        }
-        hipLaunchKernelGGL(k_wy_tw, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, w.T, a.kb, w.W, nc);
-        if (hipGetLastError() != hipSuccess) return hip_fail("wy T^T W");
-        // C -= V W
-        if (!tp) {
-            if (!gemm(bh, false, a.nv, nc, a.kb, -1.0, w.V, w.ldv, w.W, kNb, 1.0, C + k, lda)) return blas_fail();
-        } else {
-            if (!gemm(bh, false, a.kb, nc, a.kb, -1.0, w.V, w.ldv, w.W, kNb, 1.0, C + k, lda)) return blas_fail();
-            if (!gemm(bh, false, h - n, nc, a.kb, -1.0, w.V + a.kb, w.ldv, w.W, kNb, 1.0, C + n, lda))
-                return blas_fail();
+            hipLaunchKernelGGL(k_wy_tw, dim3((unsigned)((nc + 7) / 8)), dim3(256), 0, s, w.Wp, w.wp_stride,
+                               (int)wparts, w.T, a.tau, a.kb, w.W, nc);
+            if (hipGetLastError() != hipSuccess) return hip_fail("wy T^T W");
+            // C -= V W2
+            if (!tp) {
+                if (!gemm(bh, false, a.nv, nc, a.kb, -1.0, w.V, w.ldv, w.W, kNb, 1.0, C + k, lda))
+                    return blas_fail();
+            } else {
+                if (!gemm(bh, false, a.kb, nc, a.kb, -1.0, w.V, w.ldv, w.W, kNb, 1.0, C + k, lda))
+                    return blas_fail();
+                if (!gemm(bh, false, h - n, nc, a.kb, -1.0, w.V + a.kb, w.ldv, w.W, kNb, 1.0, C + n, lda))
+                    return blas_fail();
+            }
         }
     }
     return FIGARO_OK;
