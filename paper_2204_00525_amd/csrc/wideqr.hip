@@ -48,6 +48,7 @@ constexpr int kPassThreads = 256;   // threads of a panel workgroup (4 waves)
 constexpr int kSmallRows = 1024;    // virtual rows up to which one workgroup factors a panel
 constexpr int kMaxPassWgs = 128;    // workgroups of a per-column pass
 constexpr int kPartStride = kNb + 1;
+constexpr int kTpSmall = 64;        // tail rows up to which the triangular-pentagonal form has its own kernels
 
 struct PanelArgs {
     double *A;
@@ -91,9 +92,8 @@ struct Refl {
     const double *head, *tot;
 };
 
-__device__ __forceinline__ Refl make_reflector(const double *head, const double *tot) {
+__device__ __forceinline__ Refl make_reflector_scalars(double alpha, double sig2) {
     Refl r;
-    const double alpha = head[0], sig2 = tot[0];
     r.tau = 0.0;
     r.scale = 0.0;
     r.beta = alpha;
@@ -102,6 +102,13 @@ __device__ __forceinline__ Refl make_reflector(const double *head, const double 
         r.tau = (r.beta - alpha) / r.beta;
         r.scale = 1.0 / (alpha - r.beta);
     }
+    r.head = nullptr;
+    r.tot = nullptr;
+    return r;
+}
+
+__device__ __forceinline__ Refl make_reflector(const double *head, const double *tot) {
+    Refl r = make_reflector_scalars(head[0], tot[0]);
     r.head = head;
     r.tot = tot;
     return r;
@@ -258,6 +265,65 @@ __global__ __launch_bounds__(TH) void k_panel_one(PanelBatch batch) {
     }
 }
 
+// Panel of the triangular-pentagonal form with a short tail (g <= GM rows
+// below the triangle), one wave per job, one panel column per lane: lane c
+// holds the panel's own rows of its column (top, relative to the current
+// pivot row, which leaves when it is final) and the g tail rows.  The
+// sums of a reflector are then dot products within each lane over the
+// tail; the pivot column's tail is broadcast through LDS.
+template <int GM>
+__global__ __launch_bounds__(64) void k_panel_tp(PanelBatch batch) {
+    __shared__ double sx[GM];
+    __shared__ double salpha;
+    const PanelArgs a = batch.a[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int g = (int)(a.nv - a.kb);
+    const int c = lane < a.kb ? lane : a.kb - 1;   // clamped column of this lane
+    const bool live = lane < a.kb;
+    const double *col = a.A + (a.k + c) * a.lda;
+    double top[kNb], tail[GM];
+#pragma unroll
+    for (int i = 0; i < kNb; ++i) top[i] = keep_or_zero(col[a.k + (i < a.kb ? i : a.kb - 1)], live && i < a.kb);
+#pragma unroll
+    for (int r = 0; r < GM; ++r) tail[r] = keep_or_zero(col[r < g ? a.s0 + r : a.k], live && r < g);
+    for (int p = 0; p < a.kb; ++p) {
+        if (lane == p) {
+#pragma unroll
+            for (int r = 0; r < GM; ++r) sx[r] = tail[r];
+            salpha = top[0];
+        }
+        __syncthreads();
+        double x[GM];
+        double sig2 = 0.0, d = 0.0;
+#pragma unroll
+        for (int r = 0; r < GM; ++r) {
+            x[r] = sx[r];
+            sig2 += x[r] * x[r];
+            d += x[r] * tail[r];
+        }
+        const Refl rf = make_reflector_scalars(salpha, sig2);
+        // V column p: 1 on the pivot's own row, 0 on the triangle's other
+        // rows, the scaled tail below
+        for (int64_t t = lane; t < a.nv; t += 64)
+            a.V[(int64_t)p * a.ldv + t] = t < a.kb ? (t == p ? 1.0 : 0.0) : sx[t - a.kb] * rf.scale;
+        if (lane == 0) a.tau[p] = rf.tau;
+        if (live && lane > p) {
+            const double w = top[0] + rf.scale * d;
+            const double f = rf.tau * w;
+            top[0] -= f;
+            const double fv = f * rf.scale;
+#pragma unroll
+            for (int r = 0; r < GM; ++r) tail[r] -= fv * x[r];
+        }
+        if (live && lane == p) top[0] = rf.beta;
+        if (live && lane >= p) a.A[(a.k + p) + (a.k + lane) * a.lda] = top[0];
+#pragma unroll
+        for (int i = 0; i + 1 < kNb; ++i) top[i] = top[i + 1];
+        top[kNb - 1] = 0.0;
+        __syncthreads();
+    }
+}
+
 // Column step p of a tall panel; workgroup b owns virtual rows
 // [b * rows_per_wg, (b + 1) * rows_per_wg).  Partial sums and the
 // reflector's row alternate between two buffers by column parity, so a
@@ -270,6 +336,19 @@ __global__ __launch_bounds__(kPassThreads) void k_panel_pass(PanelBatch batch, i
     const int wg = blockIdx.x - batch.wg0[job];
     if (p > a.kb) return;   // a narrower panel of the batch is done
     const int q = p - 1;
+    const int c_lo = p > 0 ? q : p;
+    const int width = a.kb - c_lo;
+    const int64_t t0 = (int64_t)wg * a.rows_per_wg;
+    const int64_t t1 = std::min<int64_t>(a.nv, t0 + a.rows_per_wg);
+    // the first row's loads go out before the partial sums are read, so
+    // the two memory round trips overlap
+    double y[kNb];
+    {
+        const int64_t t = t0 + threadIdx.x < t1 ? t0 + threadIdx.x : t0;
+        const double *base = a.A + real_row(a, t < a.nv ? t : 0) + (a.k + c_lo) * a.lda;
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) y[c] = keep_or_zero(base[(int64_t)(c < width ? c : width - 1) * a.lda], c < width);
+    }
     Refl r{};
     double w[kNb];
     if (p > 0) {
@@ -290,18 +369,16 @@ __global__ __launch_bounds__(kPassThreads) void k_panel_pass(PanelBatch batch, i
         reflector_w(r, w);
         if (wg == 0 && threadIdx.x == 0) a.tau[q] = r.tau;
     }
-    const int c_lo = p > 0 ? q : p;
-    const int width = a.kb - c_lo;
-    const int64_t t0 = (int64_t)wg * a.rows_per_wg;
-    const int64_t t1 = std::min<int64_t>(a.nv, t0 + a.rows_per_wg);
     double acc[kNb];
 #pragma unroll
     for (int c = 0; c < kNb; ++c) acc[c] = 0.0;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += kPassThreads) {
         double *base = a.A + real_row(a, t) + (a.k + c_lo) * a.lda;
-        double y[kNb];
+        if (t != t0 + threadIdx.x) {
 #pragma unroll
-        for (int c = 0; c < kNb; ++c) y[c] = keep_or_zero(base[(int64_t)(c < width ? c : width - 1) * a.lda], c < width);
+            for (int c = 0; c < kNb; ++c)
+                y[c] = keep_or_zero(base[(int64_t)(c < width ? c : width - 1) * a.lda], c < width);
+        }
         if (p > 0) {
             bool changed;
             a.V[(int64_t)q * a.ldv + t] = apply_row(a, t, q, r, w, y, changed);
@@ -336,15 +413,30 @@ __global__ __launch_bounds__(256) void k_wy_g(const double *Gp, int nparts, doub
     }
 }
 
-// W2 = T^T W for the kb x nc block W, W the sum of nparts partial products
-// (part b at Wp + b * part_stride, kNb x nc, leading dimension kNb), where
-// T is the triangular factor of the compact WY form.  T is never formed:
-// its inverse is diag(1 / tau) + the strict upper triangle of V^T V (the
-// column recurrence of T, inverted block by block), so W2 solves
-// (diag(1 / tau) + strictly-lower(G^T)) W2 = W by forward substitution:
+// Forward substitution of one column through T^T: T is never formed, its
+// inverse being diag(1 / tau) plus the strict upper triangle of G = V^T V
+// (the column recurrence of T, inverted block by block), so W2 = T^T W
+// solves (diag(1 / tau) + strictly-lower(G^T)) W2 = W:
 //   W2_i = tau_i (W_i - sum_{j < i} G(j, i) W2_j),
 // which also gives W2_i = 0 for a reflector with tau_i = 0 (the identity).
-// 32 threads per column, 8 columns per workgroup.
+// Taken column by column: W2_j is final once the columns before it have
+// been subtracted.  sG[j][i] = G(i, j) in LDS (rows padded; G symmetric).
+// (An empty asm statement per column keeps the compiler from hoisting all
+// 496 LDS reads of G ahead of the arithmetic, which would spill.)
+__device__ __forceinline__ void solve_t(const double (*sG)[kNb + 1], const double *stau, double (&w)[kNb]) {
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) {
+        w[j] *= stau[j];
+#pragma unroll
+        for (int i = j + 1; i < kNb; ++i) w[i] -= sG[j][i] * w[j];
+        asm volatile("" ::: "memory");
+    }
+}
+
+// W2 = T^T W for the kb x nc block W, W the sum of nparts partial products
+// (part b at Wp + b * part_stride, kNb x nc, leading dimension kNb): 32
+// threads per column (coalesced partial sums), 8 columns per workgroup;
+// the substitution of a column runs over its 32 threads in lock step.
 __global__ __launch_bounds__(256) void k_wy_tw(const double *Wp, int64_t part_stride, int nparts, const double *G,
                                                const double *tau, int kb, double *W2, int64_t nc) {
     __shared__ double sG[kNb][kNb + 1];   // sG[q][i] = G(i, q), rows padded against bank conflicts
@@ -372,6 +464,62 @@ __global__ __launch_bounds__(256) void k_wy_tw(const double *Wp, int64_t part_st
         if (q > i) acc += sG[q][i] * sW[cl][i];   // G(i, q) W2_i
     }
     if (c < nc && q < kb) W2[c * kNb + q] = sW[cl][q];
+}
+
+// The whole trailing update of a triangular-pentagonal panel whose tail
+// has few rows (g <= kTpSmall), in one launch: for trailing column c,
+//   W = C_top[:, c] + V_S^T C_S[:, c],  W2 = T^T W,
+//   C_top[:, c] -= W2,  C_S[:, c] -= V_S W2,
+// with V = [I; V_S] (the panel's own rows of V are the identity) and
+// G = I + V_S^T V_S.  C_top: the panel's rows of the triangular block;
+// C_S: the g tail rows.  One thread per column.
+__global__ __launch_bounds__(256) void k_tp_update(const double *V, int64_t ldv, const double *tau, int kb, int g,
+                                                   double *Ctop, double *CS, int64_t lda, int64_t nc) {
+    __shared__ double sVS[kTpSmall][kNb];
+    __shared__ double sG[kNb][kNb + 1];
+    __shared__ double stau[kNb];
+    for (int e = threadIdx.x; e < kTpSmall * kNb; e += blockDim.x) {
+        const int r = e / kNb, q = e % kNb;
+        sVS[r][q] = (r < g && q < kb) ? V[(int64_t)q * ldv + kb + r] : 0.0;
+    }
+    if (threadIdx.x < kNb) stau[threadIdx.x] = threadIdx.x < kb ? tau[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+        const int i = e / kNb, j = e % kNb;
+        double s = (i == j) ? 1.0 : 0.0;
+#pragma unroll 1
+        for (int r = 0; r < g; ++r) s += sVS[r][i] * sVS[r][j];
+        sG[i][j] = s;
+    }
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    double *top = Ctop + c * lda;
+    double *cs = CS + c * lda;
+    // the panel's rows of column c, loaded and stored at clamped addresses
+    // (no branch per row): rows beyond kb repeat row kb - 1, whose own
+    // store comes last
+    double t0[kNb], w[kNb];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) t0[q] = top[q < kb ? q : kb - 1];
+#pragma unroll
+    for (int q = 0; q < kNb; ++q) w[q] = keep_or_zero(t0[q], q < kb);
+#pragma unroll 1
+    for (int r = 0; r < g; ++r) {
+        const double x = cs[r];
+#pragma unroll
+        for (int q = 0; q < kNb; ++q) w[q] += sVS[r][q] * x;
+    }
+    solve_t(sG, stau, w);   // w[q] = 0 beyond kb (tau 0 there)
+#pragma unroll
+    for (int q = kNb - 1; q >= 0; --q) top[q < kb ? q : kb - 1] = t0[q] - w[q];
+#pragma unroll 1
+    for (int r = 0; r < g; ++r) {
+        double d = 0.0;
+#pragma unroll
+        for (int q = 0; q < kNb; ++q) d += sVS[r][q] * w[q];
+        cs[r] -= d;
+    }
 }
 
 // Upper-triangular part of the first min(rows, cols) rows of src (cols
@@ -419,23 +567,30 @@ int64_t split_parts(int64_t rows) { return std::max<int64_t>(1, (rows + kSplitRo
 // Partial products P_b = V_b^T X_b (kNb x nc each, leading dimension kNb,
 // part b at P + b * part_stride) over the row slices of V (rows x kb, ldv)
 // and X (rows x nc, ldx), from part `first` on.  Returns the parts written.
+// (With only kb = 32 output rows, rocBLAS reaches the FP64 peak on these
+// slices; the products' own long dimension would give it a handful of
+// workgroups.)
 bool split_vt_x(rocblas_handle h, int kb, int64_t nc, int64_t rows, const double *V, int64_t ldv, const double *X,
                 int64_t ldx, double *P, int64_t part_stride, int64_t first, int64_t &parts) {
     parts = 0;
     if (rows <= 0 || nc <= 0) return true;
     const int64_t full = rows / kSplitRows, rem = rows - full * kSplitRows;
     const double one = 1.0, zero = 0.0;
+    const double *A = V, *B = X;
+    const int64_t lda = ldv, ldb = ldx;
+    const int64_t m = kb, n = nc, ldc = kNb;
     if (full > 0) {
-        if (rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, kb, (rocblas_int)nc,
-                                          (rocblas_int)kSplitRows, &one, V, (rocblas_int)ldv, kSplitRows, X,
-                                          (rocblas_int)ldx, kSplitRows, &zero, P + first * part_stride, kNb,
-                                          part_stride, (rocblas_int)full) != rocblas_status_success)
+        if (rocblas_dgemm_strided_batched(h, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)m,
+                                          (rocblas_int)n, (rocblas_int)kSplitRows, &one, A, (rocblas_int)lda,
+                                          kSplitRows, B, (rocblas_int)ldb, kSplitRows, &zero,
+                                          P + first * part_stride, (rocblas_int)ldc, part_stride,
+                                          (rocblas_int)full) != rocblas_status_success)
             return false;
         parts += full;
     }
     if (rem > 0) {
-        if (!gemm(h, true, kb, nc, rem, 1.0, V + full * kSplitRows, ldv, X + full * kSplitRows, ldx, 0.0,
-                  P + (first + parts) * part_stride, kNb))
+        if (!gemm(h, true, m, n, rem, 1.0, A + full * kSplitRows, lda, B + full * kSplitRows, ldb, 0.0,
+                  P + (first + parts) * part_stride, ldc))
             return false;
         parts += 1;
     }
@@ -526,14 +681,19 @@ bool panel_args(const WideQrJob &J, int64_t k, PanelArgs &a) {
 
 // One-workgroup panels: one launch per register shape, one workgroup per job.
 hipError_t launch_small_panels(const std::vector<PanelArgs> &pa, hipStream_t s) {
-    for (int shape = 0; shape < 4; ++shape) {
+    for (int shape = 0; shape < 7; ++shape) {
         PanelBatch b{};
         for (const PanelArgs &a : pa) {
-            const int sh = a.nv <= 64 ? 0 : a.nv <= kPassThreads ? 1 : a.nv <= 2 * kPassThreads ? 2 : 3;
+            const int64_t g = a.nv - a.kb;
+            const int sh = (a.tp && g <= 4) ? 4 : (a.tp && g <= 16) ? 5 : (a.tp && g <= kTpSmall) ? 6
+                           : a.nv <= 64 ? 0 : a.nv <= kPassThreads ? 1 : a.nv <= 2 * kPassThreads ? 2 : 3;
             if (sh == shape) b.a[b.count++] = a;
         }
         if (b.count == 0) continue;
         switch (shape) {
+            case 4: hipLaunchKernelGGL((k_panel_tp<4>), dim3(b.count), dim3(64), 0, s, b); break;
+            case 5: hipLaunchKernelGGL((k_panel_tp<16>), dim3(b.count), dim3(64), 0, s, b); break;
+            case 6: hipLaunchKernelGGL((k_panel_tp<kTpSmall>), dim3(b.count), dim3(64), 0, s, b); break;
             case 0: hipLaunchKernelGGL((k_panel_one<1, 64>), dim3(b.count), dim3(64), 0, s, b); break;
             case 1: hipLaunchKernelGGL((k_panel_one<1, kPassThreads>), dim3(b.count), dim3(kPassThreads), 0, s, b); break;
             case 2: hipLaunchKernelGGL((k_panel_one<2, kPassThreads>), dim3(b.count), dim3(kPassThreads), 0, s, b); break;
@@ -617,6 +777,12 @@ figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, st
             const int64_t nc = n - k - a.kb;
             if (nc <= 0) continue;
             double *C = J.A + (k + a.kb) * lda;   // trailing columns, row 0
+            if (tp && h - n <= kTpSmall) {
+                hipLaunchKernelGGL(k_tp_update, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, w.V, w.ldv,
+                                   a.tau, a.kb, (int)(h - n), C + k, C + n, lda, nc);
+                if (hipGetLastError() != hipSuccess) return hip_fail("tp update");
+                continue;
+            }
             // V^T V (split over the rows and summed)
             int64_t gparts = 0;
             if (!split_vt_x(bh, a.kb, a.kb, a.nv, w.V, w.ldv, w.V, w.ldv, w.G, kNb * kNb, 0, gparts))

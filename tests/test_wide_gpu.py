@@ -70,7 +70,30 @@ CASES = {
     # star rooted at a dimension: the fact table joins 150 columns of its
     # children (more than the in-place view holds: stored join)
     "star_dim_root_200": lambda: synth.random_star(43, 4, 3000, 200, 50, pk_dims=False, dom=20, root=1),
+    # a narrow relation of 8 and of 30 columns beside a wide one: 9 and 31
+    # rows below the final QR's triangle (its short-tail kernels)
+    "cartesian_8_150": lambda: synth.cartesian_uniform(36, 300, 8, 400, 150),
+    "cartesian_30_150_short": lambda: synth.cartesian_uniform(37, 300, 30, 400, 150),
 }
+
+
+def test_final_qr_tail_shapes_are_covered(F):
+    """The cases above reach every form of the final QR: tails of at most 4,
+    16 and 64 rows below the triangle (one-wave column panels and the fused
+    update) and longer ones (workgroup panels and GEMM updates)."""
+    import torch
+    tails = {}
+    for name, make in CASES.items():
+        inst = make()
+        plan = F.plan_from_instance(inst)
+        tails[name] = int(F.lib().figaro_debug_stack_rows(plan._handle)) - inst.n
+        plan.close()
+    _say(f"[wide] rows below the triangle: {tails}")
+    g = sorted(tails.values())
+    assert any(x <= 4 for x in g)
+    assert any(4 < x <= 16 for x in g)
+    assert any(16 < x <= 64 for x in g)
+    assert any(x > 64 for x in g)
 
 
 def _reference(oracle_lib, inst):
