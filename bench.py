@@ -132,6 +132,28 @@ def materialized_qr_ms(A, reps=3):
     return (time.perf_counter() - t0) / reps * 1e3, Rq
 
 
+def materialized_qr_fwd_bwd_ms(A, reps=2):
+    """Forward + backward of the loss R_nn^2/2 + sum log R_ii through
+    torch.linalg.qr (reduced, autograd, FP64, GPU) of a materialised join,
+    R sign-normalised as this library returns it; returns (ms, dA)."""
+    import torch
+    X = A.detach().requires_grad_(True)
+
+    def step():
+        R = torch.linalg.qr(X, mode="reduced")[1]
+        R = R * torch.sign(torch.diagonal(R)).detach()[:, None]
+        loss = 0.5 * R[-1, -1] ** 2 + torch.log(torch.diagonal(R)).sum()
+        return torch.autograd.grad(loss, X)[0]
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g = step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3, g
+
+
 def comparator(F, div: int):
     """torch.linalg.qr (FP64, GPU) of the materialised two-relation join vs
     this library, both on the workload divided by `div`, both against the
@@ -265,6 +287,10 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
         torch.cuda.synchronize()
         t_mat = time.perf_counter() - t0
         t_qr, Rq = materialized_qr_ms(A)
+        log("star join: forward + backward through the materialised QR (autograd)")
+        t_qr_fb, dA = materialized_qr_fwd_bwd_ms(A)
+        del dA
+        torch.cuda.empty_cache()
         G = A.t() @ A
         gn = torch.linalg.norm(G)
 
@@ -274,6 +300,7 @@ def star(F, steps, warmup, with_comparator, with_tree_choice=True):
         out["comparator"] = {
             "materialized_qr_ms": t_qr, "materialize_host_ms": t_mat * 1e3,
             "speedup_fwd": t_qr / (t_fwd * 1e3),
+            "materialized_qr_fwd_bwd_ms": t_qr_fb, "speedup_fwd_bwd": t_qr_fb / (t_fb * 1e3),
             "figaro_gram_residual": gram_res(R.contiguous()),
             "materialized_qr_gram_residual": gram_res(Rq),
             "rel_diff_R": float(torch.linalg.norm(R - Rq) / torch.linalg.norm(Rq)),
