@@ -198,3 +198,49 @@ def test_wide_backward_is_refused(F):
     with pytest.raises(F.FigaroError) as e:
         plan.r_backward(vals, Rt, torch.eye(plan.n, dtype=torch.float64, device="cuda"))
     assert e.value.name == "EUNSUPPORTED"
+
+
+@pytest.mark.parametrize("name", ["cartesian_30_150", "star_dim_root_200", "chain3_wide_180"])
+def test_wide_r0_theorem6(F, oracle_lib, name):
+    """R0 of a wide plan (every tail written in its global columns, 16-bit
+    column maps, the buffer cleared by the call): R0^T R0 equals A^T A of
+    the join (Theorem 6)."""
+    import torch
+    inst = CASES[name]()
+    plan = F.plan_from_instance(inst)
+    vals = F.device_values(plan, inst)
+    R0, blk = plan.r0(vals)
+    torch.cuda.synchronize()
+    R0 = R0.cpu().numpy()
+    Ghi, Glo, _ = oracle_lib.factorized_gram(inst)
+    err = relf(R0.T @ R0, Ghi + Glo)
+    _say(f"[wide] R0 case={name} rows={R0.shape[0]} gram rel={err:.2e}")
+    assert err <= 1e-12
+
+
+def test_wide_plans_in_a_batch(F):
+    """Wide and narrow plans in one batch, eager and replayed from a captured
+    graph: each R bit for bit equal to its plan run alone."""
+    import torch
+    insts = [CASES["cartesian_100_100"](), synth.config1(), CASES["chain3_wide_180"]()]
+    plans = [F.plan_from_instance(i) for i in insts]
+    vals = [F.device_values(p, i) for p, i in zip(plans, insts)]
+    alone = [p.r_factor(v).cpu().numpy() for p, v in zip(plans, vals)]
+    b = F.Batch(plans, streams=2)
+    eager = [R.cpu().numpy() for R in b.r(vals)]
+    for a, e in zip(alone, eager):
+        assert np.array_equal(a, e)
+    s = torch.cuda.Stream()
+    outs = [torch.full((p.n, p.n), np.nan, dtype=torch.float64, device="cuda") for p in plans]
+    with torch.cuda.stream(s):
+        Rg = b.capture(vals, outs, s)
+    s.synchronize()
+    for rep in range(2):
+        for o in outs:
+            o.fill_(np.nan)
+        torch.cuda.synchronize()
+        b.launch(s)
+        s.synchronize()
+        for R, a in zip(Rg, alone):
+            assert np.array_equal(R.cpu().numpy(), a), f"replay {rep}"
+    b.close()
