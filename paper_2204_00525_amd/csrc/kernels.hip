@@ -639,12 +639,12 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 // each tile of 64 coop_rpl(CW) rows; wave w holds columns [CW w, CW w + CW)
 // of the tile (coop_rpl(CW) rows per lane) and the same columns of the workgroup's R
 // (all n rows, row-major, in its LDS slice).  CW is 4 for n <= 32 (W = 6 or
-// 8), 8 for n <= 40 (W = 5) and 32 for wider matrices.  At the step of column j the wave
-// that owns j forms the reflector from its own column (for CW = 32 kept at
-// register column 0 by rotating its columns; for CW <= 8 the column loop is
-// unrolled within the block, so the owner works on the columns it still
-// holds in place) and publishes the column and the reflector's scalars through
-// LDS; after one barrier the waves to its right apply the reflector to their
+// 8), 8 for n <= 64 (W = 5 up to 40 columns, 8 above) and 16 up to 128
+// (W = 8).  At the step of column j the wave that owns j forms the
+// reflector from its own column (the column loop is unrolled within the
+// block, so the owner works on the columns it still holds in place) and
+// publishes the column and the reflector's scalars through LDS; after one
+// barrier the waves to its right apply the reflector to their
 // columns (and their part of row j of R).  The scalars and the column are
 // double-buffered by the parity of a column step count that runs on across
 // tiles, so one barrier per column suffices.  Sharing the tile
@@ -654,12 +654,14 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_dense(DenseArgs a)
 // barriers.  Workgroup b folds rows [b W', (b+1) W'), W' = tiles_per_wave *
 // 64 coop_rpl(CW) rows, into one R; the single workgroup of the last level
 // sign-normalises it.
-constexpr int kWideCols = 32;
 constexpr int kNarrowCols = 8;
-// rows per lane of a shared tile: narrow column blocks (at most 8 columns
-// per wave) hold 8 rows of each column per lane (512-row tiles, so a level
-// divides the rows by 16 at n = 32); wide blocks (32 columns per wave) 2
-constexpr int coop_rpl(int cw) { return cw <= kNarrowCols ? 8 : 2; }
+constexpr int kMidCols = 16;
+// rows per lane of a shared tile: blocks of at most 8 columns per wave hold
+// 8 rows of each column per lane (512-row tiles, so a level divides the
+// rows by 16 at n = 32), blocks of 16 columns 4 (256-row tiles).  Eight
+// waves of 16 columns cover 128: two waves per SIMD, 64 tile doubles per
+// lane.
+constexpr int coop_rpl(int cw) { return cw <= kNarrowCols ? 8 : 4; }
 
 // One column step of the shared-tile kernel with the column's place in its
 // block (JL) known at compile time (narrow blocks): the owner reduces only
@@ -777,77 +779,9 @@ __global__ __launch_bounds__(64 * W) void k_dense_coop(DenseArgs a) {
             for (int k = 0; k < RPL; ++k) x[k][c] = (live && base + k < a.rows) ? src[base + k] : 0.0;
         }
         const int par = (int)((it * n) & 1);
-        if constexpr (CW <= kNarrowCols) {   // 4 or 8 columns per wave
-            for (int o = 0; o < W; ++o)
-                coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, par, std::make_integer_sequence<int, CW>{});
-            continue;
-        }
-        for (int j = 0; j < n; ++j) {
-            const int o = j / CW, jl = j - o * CW, slot = (par + j) & 1;
-            if (wib == o) {
-                // register column k holds local column jl + k
-                double d[CW], p[CW];
-#pragma unroll
-                for (int k = 0; k < CW; ++k) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) acc = fma(x[r][0], x[r][k], acc);
-                    d[k] = acc;
-                }
-#pragma unroll
-                for (int k = 0; k < CW; ++k) {
-                    const bool in_row = k < CW - jl;
-                    const double v = rw[in_row ? j * CW + jl + k : NW * CW + k];
-                    p[k] = in_row ? v : 0.0;
-                }
-                wave_sum_batch<CW>(d);
-                const Reflector h = reflector(p[0], d[0]);
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) xb[slot][lane * RPL + r] = x[r][0];
-                sc[slot][0] = h.scale;
-                sc[slot][1] = h.ts;
-                sc[slot][2] = h.tau;
-#pragma unroll
-                for (int k = 1; k < CW; ++k) {
-                    const double w = fma(h.scale, d[k], p[k]);
-                    const double g = h.ts * w;
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, x[r][0], x[r][k]);
-                    rw[(k < CW - jl) ? j * CW + jl + k : NW * CW + k] = fma(-h.tau, w, p[k]);
-                }
-                rw[j * CW + jl] = h.rjj;
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) {
-#pragma unroll
-                    for (int k = 0; k < CW - 1; ++k) x[r][k] = x[r][k + 1];
-                    x[r][CW - 1] = 0.0;
-                }
-            }
-            __syncthreads();
-            if (wib > o) {
-                double xj[RPL], d[CW], p[CW];
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) xj[r] = xb[slot][lane * RPL + r];
-                const double scale = sc[slot][0], ts = sc[slot][1], tau = sc[slot][2];
-#pragma unroll
-                for (int k = 0; k < CW; ++k) {
-                    double acc = 0.0;
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) acc = fma(xj[r], x[r][k], acc);
-                    d[k] = acc;
-                    p[k] = rw[j * CW + k];
-                }
-                wave_sum_batch<CW>(d);
-#pragma unroll
-                for (int k = 0; k < CW; ++k) {
-                    const double w = fma(scale, d[k], p[k]);
-                    const double g = ts * w;
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) x[r][k] = fma(-g, xj[r], x[r][k]);
-                    rw[j * CW + k] = fma(-tau, w, p[k]);
-                }
-            }
-        }
+        static_assert(CW <= kMidCols, "column blocks of at most 16 columns per wave");
+        for (int o = 0; o < W; ++o)
+            coop_block<W, CW, RPL>(x, rw, xb, sc, wib, o, n, lane, par, std::make_integer_sequence<int, CW>{});
     }
     __syncthreads();   // every slice complete (the diagonal is read across slices)
     const bool fin = gridDim.x == 1 && a.final_r;
@@ -1020,7 +954,7 @@ bool dense_coop(int ncols) { return ncols > 16; }
 
 int dense_tile_rows_for(int ncols, int variant) {
     if (!dense_coop(ncols)) return tile_items_for(ncols, variant);
-    return 64 * coop_rpl(ncols <= kFusedMaxCols ? kNarrowCols : kWideCols);
+    return 64 * coop_rpl(ncols <= 64 ? kNarrowCols : kMidCols);
 }
 
 int dense_waves_per_block(int ncols) {
@@ -1058,11 +992,12 @@ hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s) {
         if (a.n <= 24) hipLaunchKernelGGL((k_dense_coop<6, 4>), grid, dim3(384), 0, s, a);
         else if (a.n <= 32) hipLaunchKernelGGL((k_dense_coop<8, 4>), grid, dim3(512), 0, s, a);
         else hipLaunchKernelGGL((k_dense_coop<5, kNarrowCols>), grid, dim3(320), 0, s, a);
+    } else if (a.n <= 64) {
+        // 8 columns per wave on 512-row tiles
+        hipLaunchKernelGGL((k_dense_coop<8, kNarrowCols>), grid, dim3(512), 0, s, a);
     } else {
-        const int w = (a.n + kWideCols - 1) / kWideCols;
-        if (w == 2) hipLaunchKernelGGL((k_dense_coop<2, kWideCols>), grid, dim3(128), 0, s, a);
-        else if (w == 3) hipLaunchKernelGGL((k_dense_coop<3, kWideCols>), grid, dim3(192), 0, s, a);
-        else hipLaunchKernelGGL((k_dense_coop<4, kWideCols>), grid, dim3(256), 0, s, a);
+        // 16 columns per wave on 256-row tiles
+        hipLaunchKernelGGL((k_dense_coop<8, kMidCols>), grid, dim3(512), 0, s, a);
     }
     return hipGetLastError();
 }
