@@ -28,11 +28,15 @@
 // A panel column needs one reduction over all its rows (the norm of x and
 // the dot products of x with the panel's later columns, from which both the
 // reflector and its effect on those columns follow).  Short panels run in
-// one workgroup; tall ones take one launch per column over many workgroups,
-// each launch first finishing the previous column's reflector from the
-// partial sums every workgroup left, applying it to its rows, then leaving
-// its partial sums for the next column.  Nothing spins on another
-// workgroup.
+// one workgroup with their rows in registers; tall ones take one launch per
+// column over many workgroups, each launch first finishing the previous
+// column's reflector from the partial sums every workgroup left, applying
+// it to its rows, then leaving its partial sums for the next column.
+// Nothing spins on another workgroup.  A triangular-pentagonal QR with few
+// rows below the triangle (one root row, for a Cartesian product) takes
+// one wave per panel, a panel column per lane, and one fused launch for
+// the trailing update.  The panels of independent QRs (a plan's per-
+// relation regions) share launches.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
 
@@ -62,7 +66,7 @@ struct PanelArgs {
     int64_t ldv;
     double *tau;    // [kb]
     double *part;   // [2][wgs][kPartStride]: per-workgroup partial sums of one column
-    double *head;   // [2][kPartStride]: the reflector's own row, columns 0..kb-1
+    double *head;   // [2][kPartStride]: the reflector's own row, from its column on
     int32_t wgs;
     int64_t rows_per_wg;
 };
