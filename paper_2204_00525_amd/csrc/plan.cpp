@@ -936,8 +936,13 @@ figaro_status finish_plan(figaro_plan_s *p) {
     // n <= 16: one tile per wave at every level (each level costs the
     // latency of two tile steps, data then merge), and a last level of at
     // most one tile per wave; a last level of one tile needs no merge at all.
-    // Shared tiles (n > 16, up to 40): the same, one shared step per level.
-    const int64_t mid_tpw = wide ? 4 : 1, final_tiles = wide ? 8 : 1;
+    // Shared tiles (n > 16): the same, one shared step per level, as long
+    // as a tile holds at least 2.7 R's worth of rows (512-row tiles up to 64
+    // columns, 256-row tiles up to 96); with 256-row tiles of more than 96
+    // columns two steps per level, so that a level still quarters the rows.
+    // (A level of t steps shrinks the rows t*tile/n-fold; the chain of
+    // dependent tile steps is shortest where t / log(t*tile/n) is least.)
+    const int64_t mid_tpw = (wide && n > 96) ? 2 : 1, final_tiles = mid_tpw;
     int64_t rows = srow;
     int64_t maxnext = 0;
     while (true) {
