@@ -244,3 +244,36 @@ def test_wide_plans_in_a_batch(F):
         for R, a in zip(Rg, alone):
             assert np.array_equal(R.cpu().numpy(), a), f"replay {rep}"
     b.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("m,ncols", [(4096, 1024), (8192, 4096)])
+def test_exp1_cells_full_size(F, m, ncols):
+    """Cells of Exp. 1's synthetic table at full size (the largest: S, T of
+    8192 x 4096, n = 8192), by the property that holds at any size: R^T R
+    equals the Gram matrix of S x T, [m S^T S, s^T t; t^T s, m T^T T] with s,
+    t the column sums (plain FP64 products on the device), and R is upper
+    triangular with a non-negative diagonal."""
+    import torch
+    _say(f"[wide] Exp. 1 cell m={m} n={ncols}")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1000003 * m + ncols)
+    S = torch.rand((ncols, m), generator=g, dtype=torch.float64, device="cuda") * 6.0 - 3.0
+    T = torch.rand((ncols, m), generator=g, dtype=torch.float64, device="cuda") * 6.0 - 3.0
+    views = [F._RelView([], torch.zeros((0, m), dtype=torch.int32, device="cuda"), ncols, -1),
+             F._RelView([], torch.zeros((0, m), dtype=torch.int32, device="cuda"), ncols, 0)]
+    plan = F.Plan(views)
+    R = plan.r_factor([plan.to_plan_order(0, S), plan.to_plan_order(1, T)]).contiguous()
+    torch.cuda.synchronize()
+    assert bool(torch.all(torch.diagonal(R) >= 0))
+    assert bool(torch.all(torch.tril(R, -1) == 0))
+    St, Tt = S.t().contiguous(), T.t().contiguous()
+    G = torch.empty((2 * ncols, 2 * ncols), dtype=torch.float64, device="cuda")
+    G[:ncols, :ncols] = m * (St.t() @ St)
+    G[ncols:, ncols:] = m * (Tt.t() @ Tt)
+    G[:ncols, ncols:] = torch.outer(St.sum(0), Tt.sum(0))
+    G[ncols:, :ncols] = G[:ncols, ncols:].t()
+    res = float(torch.linalg.norm(R.t() @ R - G) / torch.linalg.norm(G))
+    _say(f"[wide] Exp. 1 cell m={m} n={ncols} gram residual {res:.2e}")
+    assert res <= 1e-13
+    plan.close()
