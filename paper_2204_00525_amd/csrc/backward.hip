@@ -70,46 +70,66 @@ __global__ __launch_bounds__(256) void k_qr_adjoint_small(const double *R, const
     }
 }
 
-// The same for n <= 128: one workgroup of 128 threads; thread t owns column
-// t.  R is staged in LDS; W (global, n x n) holds Y = R^{-1} Phi between the
-// two triangular solves.
-__global__ __launch_bounds__(kMaxCols) void k_qr_adjoint(const double *R, const double *dR, int n, double *K,
-                                                         double *W, int32_t *status) {
-    __shared__ double sR[kMaxCols][kMaxCols + 1];
-    const int t = threadIdx.x;
-    if (t < n)
-        for (int c = 0; c < n; ++c) sR[t][c] = (c >= t) ? R[(int64_t)c * n + t] : 0.0;
-    __syncthreads();
-    if (t < n) {
-        double *w = W + (int64_t)t * n;
-        // column t of Phi: M[i][t] for i >= t, M[t][i] for i < t, with
-        // M[i][j] = sum_{k >= max(i, j)} R[i][k] dR[j][k]
-        for (int i = 0; i < n; ++i) {
-            const int a = (i >= t) ? i : t, b = (i >= t) ? t : i;
-            double m = 0.0;
-            for (int k = a; k < n; ++k) m = fma(sR[a][k], dR[(int64_t)k * n + b], m);
-            w[i] = m;
-        }
-        // Y[:, t] = R^{-1} Phi[:, t]
-        for (int i = n - 1; i >= 0; --i) {
-            double y = w[i];
-            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], w[k], y);
-            w[i] = y / sR[i][i];
+// The same for n <= 128: R and triu(dR) staged in LDS as packed upper
+// triangles (row r from column r on, 2 x 66 KB at n = 128), the n^2 entries
+// of Phi over 256 threads into W (global, n x n), then thread t < n solves
+// R Y[:, t] = Phi[:, t] in W and R K[:, t] = Y[t, :]^T.
+constexpr int kAdjPack = kMaxCols * (kMaxCols + 1) / 2;
+__device__ __forceinline__ int packed_row(int r, int n) { return r * n - r * (r - 1) / 2 - r; }
+__global__ __launch_bounds__(256) void k_qr_adjoint(const double *R, const double *dR, int n, double *K,
+                                                    double *W, int32_t *status) {
+    __shared__ double sR[kAdjPack];
+    __shared__ double sD[kAdjPack];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int r = e % n, c = e / n;
+        if (c >= r) {
+            sR[packed_row(r, n) + c] = R[e];
+            sD[packed_row(r, n) + c] = dR[e];
         }
     }
     __syncthreads();
-    if (t < n) {
+    // Phi[i][t] = M[a][b], a = max(i, t), b = min(i, t), M[a][b] = sum_{k >= a} R[a][k] dR[b][k]
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e % n, t = e / n;
+        const int a = (i >= t) ? i : t, b = (i >= t) ? t : i;
+        const double *ra = sR + packed_row(a, n), *db = sD + packed_row(b, n);
+        double m0 = 0.0, m1 = 0.0;
+        int k = a;
+        for (; k + 1 < n; k += 2) {
+            m0 = fma(ra[k], db[k], m0);
+            m1 = fma(ra[k + 1], db[k + 1], m1);
+        }
+        if (k < n) m0 = fma(ra[k], db[k], m0);
+        W[(int64_t)t * n + i] = m0 + m1;
+    }
+    __syncthreads();
+    if (tid < n) {
+        // Y[:, t] = R^{-1} Phi[:, t]
+        const int t = tid;
+        double *w = W + (int64_t)t * n;
+        for (int i = n - 1; i >= 0; --i) {
+            const double *ri = sR + packed_row(i, n);
+            double y = w[i];
+            for (int k = i + 1; k < n; ++k) y = fma(-ri[k], w[k], y);
+            w[i] = y / ri[i];
+        }
+    }
+    __syncthreads();
+    if (tid < n) {
         // K[:, t] = R^{-1} (row t of Y)
+        const int t = tid;
         double *kt = K + (int64_t)t * n;
         for (int i = n - 1; i >= 0; --i) {
+            const double *ri = sR + packed_row(i, n);
             double y = W[(int64_t)i * n + t];
-            for (int k = i + 1; k < n; ++k) y = fma(-sR[i][k], kt[k], y);
-            kt[i] = y / sR[i][i];
+            for (int k = i + 1; k < n; ++k) y = fma(-ri[k], kt[k], y);
+            kt[i] = y / ri[i];
         }
     }
-    if (t == 0) {
+    if (tid == 0) {
         int32_t singular = 0;
-        for (int i = 0; i < n; ++i) singular |= (sR[i][i] == 0.0) ? 1 : 0;
+        for (int i = 0; i < n; ++i) singular |= (sR[packed_row(i, n) + i] == 0.0) ? 1 : 0;
         status[0] = singular;
     }
 }
@@ -413,7 +433,7 @@ hipError_t helmert_bwd_wide(const HelmertBwdArgs &a, bool unit, hipStream_t s) {
 hipError_t launch_qr_adjoint(const double *R, const double *dR, int32_t n, double *K, double *W, int32_t *status,
                              hipStream_t s) {
     if (n <= kAdjSmall) hipLaunchKernelGGL(k_qr_adjoint_small, dim3(1), dim3(256), 0, s, R, dR, (int)n, K, status);
-    else hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(kMaxCols), 0, s, R, dR, (int)n, K, W, status);
+    else hipLaunchKernelGGL(k_qr_adjoint, dim3(1), dim3(256), 0, s, R, dR, (int)n, K, W, status);
     return hipGetLastError();
 }
 
