@@ -363,7 +363,36 @@ __global__ void k_join_bwd(JoinBwdArgs a) {
     const int64_t q = idx / cc;
     const int c = (int)(idx - q * cc);
     if (q >= a.child_groups[j]) return;
-    const int64_t lo = a.inv_off[j][q], hi = a.inv_off[j][q + 1];
+    double sum = 0.0;
+    if (a.nchunks[j] > 0) {
+        // long lists: the chunks' partial sums, in chunk order
+        for (int64_t k = a.chunk_off[j][q]; k < a.chunk_off[j][q + 1]; ++k) sum += a.part[j][k * cc + c];
+    } else {
+        const int64_t lo = a.inv_off[j][q], hi = a.inv_off[j][q + 1];
+        const int col = a.colpos[j][c];
+        const int32_t *inv = a.inv_idx[j];
+        const double *mult = a.mult[j];
+        for (int64_t i = lo; i < hi; ++i) {
+            const int64_t g = inv[i];
+            sum = fma(a.ds[g * a.ld_ds + col], mult[g], sum);
+        }
+    }
+    if (a.dsigma_rowmajor[j]) a.dsigma[j][q * a.ld_dsigma[j] + c] = sum;
+    else a.dsigma[j][(int64_t)c * a.ld_dsigma[j] + q] = sum;
+}
+
+// Partial sums of child j's long inverse lists: one thread per (chunk,
+// column), the chunk's kJoinChunk entries (or fewer at the end of a list)
+// in list order.
+__global__ void k_join_bwd_chunks(JoinBwdArgs a, int j) {
+    const int cc = a.child_cols[j];
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = idx / cc;
+    const int c = (int)(idx - k * cc);
+    if (k >= a.nchunks[j]) return;
+    const int64_t q = a.chunk_q[j][k];
+    const int64_t lo = a.inv_off[j][q] + (k - a.chunk_off[j][q]) * kJoinChunk;
+    const int64_t hi = std::min<int64_t>(a.inv_off[j][q + 1], lo + kJoinChunk);
     const int col = a.colpos[j][c];
     const int32_t *inv = a.inv_idx[j];
     const double *mult = a.mult[j];
@@ -372,8 +401,7 @@ __global__ void k_join_bwd(JoinBwdArgs a) {
         const int64_t g = inv[i];
         sum = fma(a.ds[g * a.ld_ds + col], mult[g], sum);
     }
-    if (a.dsigma_rowmajor[j]) a.dsigma[j][q * a.ld_dsigma[j] + c] = sum;
-    else a.dsigma[j][(int64_t)c * a.ld_dsigma[j] + q] = sum;
+    a.part[j][k * cc + c] = sum;
 }
 
 // Root rows h_g = s_g / sqrt(c_g): dh_g = h_g K, so ds_g[c] = (s_g . K[:, c]) / c_g.
@@ -458,6 +486,12 @@ hipError_t launch_join_bwd(const JoinBwdArgs &a_in, hipStream_t s) {
     const int64_t blocks = a.part_block0[a.nchildren + 1];
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    for (int j = 0; j < a.nchildren; ++j) {
+        if (a.nchunks[j] <= 0) continue;
+        const int64_t cb = (a.nchunks[j] * a.child_cols[j] + bs - 1) / bs;
+        if (cb > 0x7fffffff) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_join_bwd_chunks, dim3((unsigned)cb), dim3(bs), 0, s, a, j);
+    }
     hipLaunchKernelGGL(k_join_bwd, dim3((unsigned)blocks), dim3(bs), 0, s, a);
     return hipGetLastError();
 }

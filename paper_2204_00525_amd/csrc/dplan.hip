@@ -1136,6 +1136,13 @@ figaro_status build_keys_on_device(figaro_plan_s *p, const figaro_relation_desc 
                 DP_LAUNCH(k_i32_from_i64, R.G, pay, R.G, idx);
                 R.d_inv_off.push_back(off);
                 R.d_inv_idx.push_back(idx);
+                // the chunking of long inverse lists is planned on the host
+                std::vector<int64_t> off_h(Pc + 1);
+                if (hipMemcpyAsync(off_h.data(), off, sizeof(int64_t) * (size_t)(Pc + 1), hipMemcpyDeviceToHost, s) !=
+                        hipSuccess ||
+                    hipStreamSynchronize(s) != hipSuccess)
+                    return set_error(p, FIGARO_EHIP, "copying the inverse child index offsets");
+                if ((st = join_chunks(p, R, c, off_h)) != FIGARO_OK) return st;
             }
             if (R.parent >= 0 && R.P < R.G) {   // project_away_join_attributes: weighted items
                 R.a4.active = true;

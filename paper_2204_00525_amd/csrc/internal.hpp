@@ -207,6 +207,14 @@ struct JoinBwdArgs {
     const int64_t *inv_off[kMaxChildren];   // [child groups + 1]
     const int32_t *inv_idx[kMaxChildren];   // parent key groups sorted by child group
     const double *mult[kMaxChildren];
+    // children whose inverse lists run long: the lists cut into chunks of
+    // kJoinChunk entries (chunk k belongs to child group chunk_q[k]; the
+    // chunks of group q are chunk_off[q] .. chunk_off[q + 1] - 1), a
+    // partial sum per (chunk, column) in part, summed in chunk order
+    int64_t nchunks[kMaxChildren];           // 0: one thread per child group walks its list
+    const int64_t *chunk_off[kMaxChildren];
+    const int32_t *chunk_q[kMaxChildren];
+    double *part[kMaxChildren];              // [nchunks][child columns]
     int64_t part_block0[kMaxChildren + 2];   // first block of every part (set by the launcher)
 };
 
@@ -357,6 +365,12 @@ struct RelPlan {
     double *d_gs = nullptr;          // gradient of s, [nsub][G]
     std::vector<int64_t *> d_inv_off;   // per child: [P_child+1]
     std::vector<int32_t *> d_inv_idx;   // per child: [G]
+    // per child: the inverse lists in chunks, where some list is longer
+    // than kJoinChunk (else nchunks 0 and null pointers)
+    std::vector<int64_t> join_nchunks;
+    std::vector<int64_t *> d_chunk_off;
+    std::vector<int32_t *> d_chunk_q;
+    std::vector<double *> d_join_part;
     // projection onto X_p
     Task a4;
     // root
@@ -474,6 +488,12 @@ inline hipError_t dev_alloc(figaro_plan_s *p, void **dst, size_t bytes) {
 
 
 figaro_status set_error(figaro_plan_s *p, figaro_status st, const std::string &msg);
+
+// Inverse lists longer than this are summed in chunks by the join adjoint.
+constexpr int64_t kJoinChunk = 1024;
+// Chunks of relation R's inverse list for child c from its offsets (host
+// copy, P_child + 1 entries), appended to R's per-child vectors (plan.cpp).
+figaro_status join_chunks(figaro_plan_s *p, RelPlan &R, size_t c, const std::vector<int64_t> &off);
 
 // Levels of a segmented head/tail task from level `first` on (plan.cpp):
 // items grouped by group_off (ngroups + 1 offsets), per-item counts (empty:

@@ -291,6 +291,36 @@ figaro_status build_task(figaro_plan_s *p, Task &T, int64_t items, const std::ve
 
 }  // namespace
 
+figaro_status join_chunks(figaro_plan_s *p, RelPlan &R, size_t c, const std::vector<int64_t> &off) {
+    const int64_t Pc = (int64_t)off.size() - 1;
+    int64_t longest = 0;
+    for (int64_t q = 0; q < Pc; ++q) longest = std::max(longest, off[q + 1] - off[q]);
+    if (longest <= kJoinChunk) {
+        R.join_nchunks.push_back(0);
+        R.d_chunk_off.push_back(nullptr);
+        R.d_chunk_q.push_back(nullptr);
+        R.d_join_part.push_back(nullptr);
+        return FIGARO_OK;
+    }
+    std::vector<int64_t> coff(Pc + 1, 0);
+    for (int64_t q = 0; q < Pc; ++q) coff[q + 1] = coff[q] + (off[q + 1] - off[q] + kJoinChunk - 1) / kJoinChunk;
+    std::vector<int32_t> cq(coff[Pc]);
+    for (int64_t q = 0; q < Pc; ++q)
+        for (int64_t k = coff[q]; k < coff[q + 1]; ++k) cq[k] = (int32_t)q;
+    int64_t *dco = nullptr;
+    int32_t *dcq = nullptr;
+    double *part = nullptr;
+    const int64_t cols = p->rel[R.children[c]].nsub;
+    if (dev_upload(p, &dco, coff) != hipSuccess || dev_upload(p, &dcq, cq) != hipSuccess ||
+        dev_alloc(p, (void **)&part, sizeof(double) * (size_t)coff[Pc] * (size_t)cols) != hipSuccess)
+        return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+    R.join_nchunks.push_back(coff[Pc]);
+    R.d_chunk_off.push_back(dco);
+    R.d_chunk_q.push_back(dcq);
+    R.d_join_part.push_back(part);
+    return FIGARO_OK;
+}
+
 figaro_status finish_task(figaro_plan_s *p, Task &T, int32_t n_total) {
     std::vector<int32_t> inv(n_total, -1);
     for (size_t q = 0; q < T.cols.size(); ++q) inv[T.cols[q]] = (int32_t)q;
@@ -807,6 +837,7 @@ figaro_status build(figaro_plan_s *p, int32_t r, const figaro_relation_desc *rel
                     return set_error(p, FIGARO_ENOMEM, "hipMalloc");
                 R.d_inv_off.push_back(doff);
                 R.d_inv_idx.push_back(didx);
+                if (figaro_status st = join_chunks(p, R, c, off); st != FIGARO_OK) return st;
             }
             if (R.parent >= 0 && R.P < R.G) {
                 R.a4.active = true;

@@ -450,6 +450,10 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
                 j.colpos[c] = Rl.d_colpos[c];
                 j.inv_off[c] = Rl.d_inv_off[c];
                 j.inv_idx[c] = Rl.d_inv_idx[c];
+                j.nchunks[c] = Rl.join_nchunks[c];
+                j.chunk_off[c] = Rl.d_chunk_off[c];
+                j.chunk_q[c] = Rl.d_chunk_q[c];
+                j.part[c] = Rl.d_join_part[c];
                 j.mult[c] = Rl.d_mult[c];
             }
             ProfScope ps(p, s, 6, 16.0 * (double)Rl.G * Rl.nsub, 0.0);
