@@ -74,6 +74,10 @@ CASES = {
     # rows below the final QR's triangle (its short-tail kernels)
     "cartesian_8_150": lambda: synth.cartesian_uniform(36, 300, 8, 400, 150),
     "cartesian_30_150_short": lambda: synth.cartesian_uniform(37, 300, 30, 400, 150),
+    # nine dimensions of 45 columns with about 40 tails each: more regions
+    # than one panel launch batches (they are taken eight at a time), each
+    # with fewer tails than columns
+    "star_nine_wide_dims": lambda: synth.random_star(44, 10, 400, 60, 45, pk_dims=False, dom=20),
 }
 
 
@@ -247,12 +251,14 @@ def test_wide_plans_in_a_batch(F):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("m,ncols", [(4096, 1024), (8192, 4096)])
+@pytest.mark.parametrize("m,ncols", [(4096, 1024), (8192, 4096), (2048, 8192)])
 def test_exp1_cells_full_size(F, m, ncols):
     """Cells of Exp. 1's synthetic table at full size (the largest: S, T of
-    8192 x 4096, n = 8192), by the property that holds at any size: R^T R
-    equals the Gram matrix of S x T, [m S^T S, s^T t; t^T s, m T^T T] with s,
-    t the column sums (plain FP64 products on the device), and R is upper
+    8192 x 4096, n = 8192), and the widest plan the library takes (S, T of
+    2048 x 8192, n = 16384: regions of fewer tails than columns, a rank-
+    deficient join), by the property that holds at any size: R^T R equals
+    the Gram matrix of S x T, [m S^T S, s^T t; t^T s, m T^T T] with s, t the
+    column sums (plain FP64 products on the device), and R is upper
     triangular with a non-negative diagonal."""
     import torch
     _say(f"[wide] Exp. 1 cell m={m} n={ncols}")
