@@ -99,6 +99,13 @@ struct HelmertArgs {
     int32_t join;
     int32_t join_col0;
     JoinSrc js;
+    // a task of more than kFusedMaxCols columns (tails not folded): one
+    // launch takes all of its kChunkCols-column chunks, blockIdx.y the chunk
+    // (0: not chunked).  Output column of task column c: c itself
+    // (cols_ident, a region) or wide_colmap[c].
+    int32_t wide_cols;
+    int32_t cols_ident;
+    const uint16_t *wide_colmap;
 };
 
 // Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
@@ -320,6 +327,7 @@ struct Task {
     int32_t ncols = 0;
     int32_t block_id = 0;
     std::vector<int32_t> cols;    // global columns, ascending
+    uint16_t *d_cols16 = nullptr; // cols on the device (tasks of more than kFusedMaxCols columns)
     int32_t *d_colmap = nullptr;
     int32_t *d_inv_colmap = nullptr;
     std::vector<Level> levels;

@@ -481,6 +481,17 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     TailSrc src = tail_src(a);
     src.pieces_out = a.pieces_out;
     src.ld_pieces = a.ld_pieces;
+    // column chunk of a wide task: task columns c0 .. c0 + NB - 1
+    int c0 = 0, join_col0 = a.join_col0;
+    if constexpr (!FUSE) {
+        if (a.wide_cols > 0) {
+            c0 = (int)blockIdx.y * NB;
+            src.ncols = min(NB, a.wide_cols - c0);
+            if (src.in) src.in += (int64_t)c0 * a.ld_in;
+            if (src.pieces_out) src.pieces_out += (int64_t)c0 * a.ld_pieces;
+            join_col0 += c0;
+        }
+    }
 
     // chunk boundaries (and first pieces) of chunks wbase .. wbase + 63, one
     // per lane, read out with readlane: no wait on a global load between
@@ -538,7 +549,8 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                 stage_read<NB, RPL, MODE>(src, cs, staged_p0, st, lane, x, ti, cf);
                 asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
             } else {
-                tile_load<NB, RPL, MODE, JOIN>(src, cs, ce, lane, x, ti, cf, &a.js, a.join_col0);
+                if constexpr (FUSE) tile_load<NB, RPL, MODE, JOIN>(src, cs, ce, lane, x, ti, cf, &a.js, a.join_col0);
+                else tile_load<NB, RPL, MODE, JOIN>(src, cs, ce, lane, x, ti, cf, &a.js, join_col0);
                 if constexpr (JOIN && FUSE) {
                     if (it + 1 < n_data) {
                         int64_t ncs, nce;
@@ -562,11 +574,18 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
                     if (!ti.valid[k] || !a.r0) continue;
                     const int64_t row = a.r0_row0 + base + k;
 #pragma unroll
-                    for (int c = 0; c < NB; ++c)
-                        if (c < a.ncols) a.r0[(int64_t)a.colmap[c] * a.ld_r0 + row] = x[k][c];
-                    for (int h = 0; h < 2; ++h)
-                        for (uint64_t m = a.other_cols[h]; m; m &= m - 1)
-                            a.r0[(int64_t)(64 * h + __builtin_ctzll(m)) * a.ld_r0 + row] = 0.0;
+                    for (int c = 0; c < NB; ++c) {
+                        if (c >= src.ncols) continue;
+                        const int oc = a.wide_cols == 0 ? a.colmap[c]
+                                       : a.cols_ident ? c0 + c : a.wide_colmap[c0 + c];
+                        a.r0[(int64_t)oc * a.ld_r0 + row] = x[k][c];
+                    }
+                    // the columns outside the task: zeros, written by the
+                    // first chunk
+                    if (c0 == 0)
+                        for (int h = 0; h < 2; ++h)
+                            for (uint64_t m = a.other_cols[h]; m; m &= m - 1)
+                                a.r0[(int64_t)(64 * h + __builtin_ctzll(m)) * a.ld_r0 + row] = 0.0;
                     if (a.block_of_row) a.block_of_row[row] = a.block_id;
                 }
                 continue;
@@ -885,7 +904,10 @@ template <int NB, int V>
 hipError_t helmert_nb(const HelmertArgs &a, bool unit, bool fuse, hipStream_t s) {
     constexpr int RPL = Shape<NB, V>::RPL, OCC = Shape<NB, V>::OCC;
     constexpr bool ROT = Shape<NB, V>::ROT;
-    dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock), block(64 * kWavesPerBlock);
+    // a wide task's column chunks side by side (never fused)
+    if (a.wide_cols > 0 && (fuse || a.ncols != NB)) return hipErrorInvalidValue;
+    const unsigned chunks = a.wide_cols > 0 ? (unsigned)((a.wide_cols + NB - 1) / NB) : 1u;
+    dim3 grid((a.waves + kWavesPerBlock - 1) / kWavesPerBlock, chunks), block(64 * kWavesPerBlock);
     if (a.join) {
         // joined heads are key groups with counts: weighted tails only
         if (unit) return hipErrorInvalidValue;

@@ -924,6 +924,13 @@ figaro_status finish_plan(figaro_plan_s *p) {
     }
     p->stack_rows = srow;
     p->r0_rows = r0row;
+    // device column tables of the wide tasks (their chunks share a launch)
+    for (auto &R : p->rel)
+        for (Task *T : {&R.a2, &R.a4}) {
+            if (!T->active || T->ncols <= kFusedMaxCols) continue;
+            std::vector<uint16_t> c16(T->cols.begin(), T->cols.end());
+            if (dev_upload(p, &T->d_cols16, c16) != hipSuccess) return set_error(p, FIGARO_ENOMEM, "hipMalloc");
+        }
     if (p->wide) {
         // workspaces: the final QR's, then one per region (their panels
         // share launches, so each keeps its reflectors apart)

@@ -147,19 +147,17 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
             if (!wide) {
                 FIGARO_TRY(launch_helmert(a, L.unit, fold, L.variant, s));
             } else {
-                // column chunks: the tails of every column depend on that
-                // column only; the first chunk also writes the zeros of the
-                // columns outside the task
-                for (int c0 = 0; c0 < T.ncols; c0 += kChunkCols) {
-                    HelmertArgs ac = a;
-                    ac.in = a.join ? nullptr : cur + (int64_t)c0 * ld;
-                    ac.join_col0 = c0;
-                    ac.ncols = std::min(kChunkCols, T.ncols - c0);
-                    ac.pieces_out = L.d_pieces + (int64_t)c0 * L.npieces;
-                    for (int c = 0; c < ac.ncols; ++c) ac.colmap[c] = (uint16_t)(region ? c0 + c : T.cols[c0 + c]);
-                    if (c0 > 0) ac.other_cols[0] = ac.other_cols[1] = 0;
-                    FIGARO_TRY(launch_helmert(ac, L.unit, false, L.variant, s));
-                }
+                // column chunks, all in one launch: the tails of every
+                // column depend on that column only; the first chunk also
+                // writes the zeros of the columns outside the task
+                if (!T.d_cols16) return set_error(p, FIGARO_EINVAL, "wide task without a device column table");
+                a.in = a.join ? nullptr : cur;
+                a.join_col0 = 0;
+                a.ncols = kChunkCols;
+                a.wide_cols = T.ncols;
+                a.cols_ident = region ? 1 : 0;
+                a.wide_colmap = T.d_cols16;
+                FIGARO_TRY(launch_helmert(a, L.unit, false, L.variant, s));
             }
         }
         cur = L.d_pieces;
