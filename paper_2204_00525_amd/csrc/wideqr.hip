@@ -269,15 +269,24 @@ __global__ __launch_bounds__(TH) void k_panel_one(PanelBatch batch) {
     }
 }
 
+// A double of lane `src` (wave-uniform) in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
 // Panel of the triangular-pentagonal form with a short tail (g <= GM rows
 // below the triangle), one wave per job, one panel column per lane: lane c
 // holds the panel's own rows of its column (top, relative to the current
 // pivot row, which leaves when it is final) and the g tail rows.  The
 // sums of a reflector are then dot products within each lane over the
-// tail; the pivot column's tail is broadcast through LDS.
+// tail; the pivot column's tail goes to every lane by lane reads (up to 16
+// rows: no LDS round trip and no barrier per column) or through LDS.
 template <int GM>
 __global__ __launch_bounds__(64) void k_panel_tp(PanelBatch batch) {
-    __shared__ double sx[GM];
+    constexpr bool BCAST = GM <= 16;
+    __shared__ double sx[BCAST ? 1 : GM];
     __shared__ double salpha;
     const PanelArgs a = batch.a[blockIdx.x];
     const int lane = threadIdx.x;
@@ -291,25 +300,42 @@ __global__ __launch_bounds__(64) void k_panel_tp(PanelBatch batch) {
 #pragma unroll
     for (int r = 0; r < GM; ++r) tail[r] = keep_or_zero(col[r < g ? a.s0 + r : a.k], live && r < g);
     for (int p = 0; p < a.kb; ++p) {
-        if (lane == p) {
+        double x[GM], alpha;
+        if constexpr (BCAST) {
 #pragma unroll
-            for (int r = 0; r < GM; ++r) sx[r] = tail[r];
-            salpha = top[0];
+            for (int r = 0; r < GM; ++r) x[r] = readlane_f64(tail[r], p);
+            alpha = readlane_f64(top[0], p);
+        } else {
+            if (lane == p) {
+#pragma unroll
+                for (int r = 0; r < GM; ++r) sx[r] = tail[r];
+                salpha = top[0];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < GM; ++r) x[r] = sx[r];
+            alpha = salpha;
         }
-        __syncthreads();
-        double x[GM];
         double sig2 = 0.0, d = 0.0;
 #pragma unroll
         for (int r = 0; r < GM; ++r) {
-            x[r] = sx[r];
             sig2 += x[r] * x[r];
             d += x[r] * tail[r];
         }
-        const Refl rf = make_reflector_scalars(salpha, sig2);
+        const Refl rf = make_reflector_scalars(alpha, sig2);
         // V column p: 1 on the pivot's own row, 0 on the triangle's other
         // rows, the scaled tail below
-        for (int64_t t = lane; t < a.nv; t += 64)
-            a.V[(int64_t)p * a.ldv + t] = t < a.kb ? (t == p ? 1.0 : 0.0) : sx[t - a.kb] * rf.scale;
+        if constexpr (BCAST) {
+            if (lane < a.kb) a.V[(int64_t)p * a.ldv + lane] = lane == p ? 1.0 : 0.0;
+            if (lane == p) {
+#pragma unroll
+                for (int r = 0; r < GM; ++r)
+                    if (r < g) a.V[(int64_t)p * a.ldv + a.kb + r] = tail[r] * rf.scale;
+            }
+        } else {
+            for (int64_t t = lane; t < a.nv; t += 64)
+                a.V[(int64_t)p * a.ldv + t] = t < a.kb ? (t == p ? 1.0 : 0.0) : sx[t - a.kb] * rf.scale;
+        }
         if (lane == 0) a.tau[p] = rf.tau;
         if (live && lane > p) {
             const double w = top[0] + rf.scale * d;
@@ -324,7 +350,7 @@ __global__ __launch_bounds__(64) void k_panel_tp(PanelBatch batch) {
 #pragma unroll
         for (int i = 0; i + 1 < kNb; ++i) top[i] = top[i + 1];
         top[kNb - 1] = 0.0;
-        __syncthreads();
+        if constexpr (!BCAST) __syncthreads();
     }
 }
 
@@ -476,12 +502,18 @@ __global__ __launch_bounds__(256) void k_wy_tw(const double *Wp, int64_t part_st
 //   C_top[:, c] -= W2,  C_S[:, c] -= V_S W2,
 // with V = [I; V_S] (the panel's own rows of V are the identity) and
 // G = I + V_S^T V_S.  C_top: the panel's rows of the triangular block;
-// C_S: the g tail rows.  One thread per column.
+// C_S: the g tail rows.  32 lanes per column (lane q: panel row q, so the
+// column's panel rows are one contiguous load), 8 columns per workgroup;
+// T^T is applied by forward substitution through its inverse, one row per
+// step, W2_i going from lane i to the other lanes by a shuffle:
+//   W2_i = tau_i (W_i - sum_{j < i} G(j, i) W2_j).
+constexpr int kTpCols = 8;   // columns per workgroup of k_tp_update
 __global__ __launch_bounds__(256) void k_tp_update(const double *V, int64_t ldv, const double *tau, int kb, int g,
                                                    double *Ctop, double *CS, int64_t lda, int64_t nc) {
     __shared__ double sVS[kTpSmall][kNb];
     __shared__ double sG[kNb][kNb + 1];
     __shared__ double stau[kNb];
+    __shared__ double sW[kTpCols][kNb];
     for (int e = threadIdx.x; e < kTpSmall * kNb; e += blockDim.x) {
         const int r = e / kNb, q = e % kNb;
         sVS[r][q] = (r < g && q < kb) ? V[(int64_t)q * ldv + kb + r] : 0.0;
@@ -496,33 +528,33 @@ __global__ __launch_bounds__(256) void k_tp_update(const double *V, int64_t ldv,
         sG[i][j] = s;
     }
     __syncthreads();
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    double *top = Ctop + c * lda;
-    double *cs = CS + c * lda;
-    // the panel's rows of column c, loaded and stored at clamped addresses
-    // (no branch per row): rows beyond kb repeat row kb - 1, whose own
-    // store comes last
-    double t0[kNb], w[kNb];
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) t0[q] = top[q < kb ? q : kb - 1];
-#pragma unroll
-    for (int q = 0; q < kNb; ++q) w[q] = keep_or_zero(t0[q], q < kb);
+    const int q = threadIdx.x & (kNb - 1), cl = threadIdx.x / kNb;
+    const int64_t c = (int64_t)blockIdx.x * kTpCols + cl;
+    const bool live = c < nc;
+    double *top = Ctop + (live ? c : 0) * lda;
+    double *cs = CS + (live ? c : 0) * lda;
+    const double t0 = (live && q < kb) ? top[q] : 0.0;
+    double w = t0;
 #pragma unroll 1
-    for (int r = 0; r < g; ++r) {
-        const double x = cs[r];
-#pragma unroll
-        for (int q = 0; q < kNb; ++q) w[q] += sVS[r][q] * x;
+    for (int r = 0; r < g; ++r) w += sVS[r][q] * (live ? cs[r] : 0.0);
+    const double tq = stau[q];   // 0 beyond kb: those lanes keep W2 = 0
+    double acc = 0.0, w2 = 0.0;
+#pragma unroll 1
+    for (int i = 0; i < kb; ++i) {
+        const double b = __shfl(tq * (w - acc), i, kNb);   // W2_i, final on lane i
+        if (q == i) w2 = b;
+        if (q > i) acc += sG[i][q] * b;
     }
-    solve_t(sG, stau, w);   // w[q] = 0 beyond kb (tau 0 there)
-#pragma unroll
-    for (int q = kNb - 1; q >= 0; --q) top[q < kb ? q : kb - 1] = t0[q] - w[q];
+    if (live && q < kb) top[q] = t0 - w2;
+    sW[cl][q] = w2;
+    __syncthreads();
+    // C_S[r] -= sum_q V_S[r][q] W2_q, lane r of the column's 32
 #pragma unroll 1
-    for (int r = 0; r < g; ++r) {
+    for (int r = q; r < g; r += kNb) {
         double d = 0.0;
 #pragma unroll
-        for (int q = 0; q < kNb; ++q) d += sVS[r][q] * w[q];
-        cs[r] -= d;
+        for (int k = 0; k < kNb; ++k) d += sVS[r][k] * sW[cl][k];
+        if (live) cs[r] -= d;
     }
 }
 
@@ -782,7 +814,7 @@ figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, st
             if (nc <= 0) continue;
             double *C = J.A + (k + a.kb) * lda;   // trailing columns, row 0
             if (tp && h - n <= kTpSmall) {
-                hipLaunchKernelGGL(k_tp_update, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, w.V, w.ldv,
+                hipLaunchKernelGGL(k_tp_update, dim3((unsigned)((nc + kTpCols - 1) / kTpCols)), dim3(256), 0, s, w.V, w.ldv,
                                    a.tau, a.kb, (int)(h - n), C + k, C + n, lda, nc);
                 if (hipGetLastError() != hipSuccess) return hip_fail("tp update");
                 continue;
