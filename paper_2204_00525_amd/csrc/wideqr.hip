@@ -427,6 +427,39 @@ __global__ __launch_bounds__(kPassThreads) void k_panel_pass(PanelBatch batch, i
     if (p < a.kb) block_sum<kPassThreads>(acc, buf, a.part + ((int64_t)(p & 1) * a.wgs + wg) * kPartStride);
 }
 
+// Partial Gram products of a panel's reflectors, P_b = V_b^T V_b over the
+// virtual rows [b kGramRows, (b + 1) kGramRows) (V: kb live columns of
+// leading dimension ldv, nv rows; columns from kb on count as zero), part b
+// at P + b * kNb * kNb, summed by k_wy_g.  The rows are staged in LDS once;
+// thread t forms four entries of row t / 8.
+constexpr int kGramRows = 128;
+__global__ __launch_bounds__(256) void k_vtv_parts(const double *V, int64_t ldv, int kb, int64_t nv, double *P) {
+    __shared__ double sV[kNb][kGramRows + 1];
+    const int64_t r0 = (int64_t)blockIdx.x * kGramRows;
+    for (int e = threadIdx.x; e < kNb * kGramRows; e += blockDim.x) {
+        const int c = e / kGramRows, r = e % kGramRows;
+        sV[c][r] = (c < kb && r0 + r < nv) ? V[(int64_t)c * ldv + r0 + r] : 0.0;
+    }
+    __syncthreads();
+    const int i = threadIdx.x >> 3, j = (threadIdx.x & 7) * 4;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 8
+    for (int r = 0; r < kGramRows; ++r) {
+        const double v = sV[i][r];
+        a0 = fma(v, sV[j][r], a0);
+        a1 = fma(v, sV[j + 1][r], a1);
+        a2 = fma(v, sV[j + 2][r], a2);
+        a3 = fma(v, sV[j + 3][r], a3);
+    }
+    double *out = P + (int64_t)blockIdx.x * kNb * kNb + i * kNb + j;
+    out[0] = a0;
+    out[1] = a1;
+    out[2] = a2;
+    out[3] = a3;
+}
+
+int64_t gram_parts(int64_t rows) { return std::max<int64_t>(1, (rows + kGramRows - 1) / kGramRows); }
+
 // G = V^T V from its nparts partial products (part b at Gp + b * kNb * kNb).
 __global__ __launch_bounds__(256) void k_wy_g(const double *Gp, int nparts, double *G) {
     for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
@@ -644,7 +677,7 @@ int64_t wide_qr_workspace_doubles(int64_t max_nv, int32_t n) {
     return (int64_t)kNb * max_nv                          // V
            + n                                            // tau
            + kNb * kNb                                    // T
-           + parts * kNb * kNb                            // partial V^T V
+           + gram_parts(max_nv) * kNb * kNb               // partial V^T V
            + (int64_t)kNb * n                             // W2
            + parts * kNb * std::max<int64_t>(n, kNb)      // partial V^T C
            + 2 * kMaxPassWgs * kPartStride + 2 * kPartStride;
@@ -657,7 +690,7 @@ figaro_status wide_qr_init(WideQr &w, double *ws, int64_t max_nv, int32_t n, voi
     w.tau = w.V + kNb * w.ldv;
     w.T = w.tau + n;
     w.G = w.T + kNb * kNb;
-    w.W = w.G + parts * kNb * kNb;
+    w.W = w.G + gram_parts(w.ldv) * kNb * kNb;
     w.Wp = w.W + (int64_t)kNb * n;
     w.wp_stride = kNb * std::max<int64_t>(n, kNb);
     w.part = w.Wp + parts * w.wp_stride;
@@ -820,9 +853,10 @@ figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, st
                 continue;
             }
             // V^T V (split over the rows and summed)
-            int64_t gparts = 0;
-            if (!split_vt_x(bh, a.kb, a.kb, a.nv, w.V, w.ldv, w.V, w.ldv, w.G, kNb * kNb, 0, gparts))
-                return blas_fail();
+            const int64_t gparts = gram_parts(a.nv);
+            hipLaunchKernelGGL(k_vtv_parts, dim3((unsigned)gparts), dim3(256), 0, s, w.V, w.ldv, (int)a.kb, a.nv,
+                               w.G);
+            if (hipGetLastError() != hipSuccess) return hip_fail("V^T V");
             hipLaunchKernelGGL(k_wy_g, dim3(1), dim3(256), 0, s, w.G, (int)gparts, w.T);
             if (hipGetLastError() != hipSuccess) return hip_fail("wy G");
             // W2 = T^T V^T C over the panel's rows and the tail rows (split
