@@ -460,9 +460,10 @@ __global__ __launch_bounds__(256) void k_vtv_parts(const double *V, int64_t ldv,
 
 int64_t gram_parts(int64_t rows) { return std::max<int64_t>(1, (rows + kGramRows - 1) / kGramRows); }
 
-// G = V^T V from its nparts partial products (part b at Gp + b * kNb * kNb).
+// G = V^T V from its nparts partial products (part b at Gp + b * kNb * kNb);
+// workgroup b sums the entries [256 b, 256 b + 256).
 __global__ __launch_bounds__(256) void k_wy_g(const double *Gp, int nparts, double *G) {
-    for (int e = threadIdx.x; e < kNb * kNb; e += blockDim.x) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < kNb * kNb; e += gridDim.x * blockDim.x) {
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         int b = 0;
         for (; b + 4 <= nparts; b += 4) {
@@ -857,7 +858,7 @@ figaro_status wide_qr_many(const std::vector<WideQrJob> &jobs, hipStream_t s, st
             hipLaunchKernelGGL(k_vtv_parts, dim3((unsigned)gparts), dim3(256), 0, s, w.V, w.ldv, (int)a.kb, a.nv,
                                w.G);
             if (hipGetLastError() != hipSuccess) return hip_fail("V^T V");
-            hipLaunchKernelGGL(k_wy_g, dim3(1), dim3(256), 0, s, w.G, (int)gparts, w.T);
+            hipLaunchKernelGGL(k_wy_g, dim3(kNb * kNb / 256), dim3(256), 0, s, w.G, (int)gparts, w.T);
             if (hipGetLastError() != hipSuccess) return hip_fail("wy G");
             // W2 = T^T V^T C over the panel's rows and the tail rows (split
             // products, summed with the T^T product)
