@@ -108,6 +108,15 @@ struct HelmertArgs {
     const uint16_t *wide_colmap;
 };
 
+// Upper head/tail levels of independent tasks in one launch (kernel
+// arguments stay under 4 KB): task t owns workgroups [wg0[t], wg0[t + 1]).
+constexpr int kHelmertBatch = 3;
+struct HelmertBatch {
+    HelmertArgs a[kHelmertBatch];
+    int32_t wg0[kHelmertBatch + 1];
+    int32_t count;
+};
+
 // Dense TSQR step: QR of `rows` rows of `in` ([n][ld_in]); workgroup b (of
 // `waves` workgroups; n <= 16: 4 waves on separate tiles, tiles_per_wave
 // tiles per wave; n > 16: waves sharing each tile, tiles_per_wave tiles per
@@ -245,6 +254,10 @@ struct WideQr;
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
 hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s);
+// Weighted unfused levels of up to kHelmertBatch tasks of one tile shape
+// (columns <= kFusedMaxCols, same nb_for(ncols) and variant).
+hipError_t launch_helmert_batch(const HelmertBatch &b, int variant, hipStream_t s);
+int helmert_shape_class(int ncols);
 hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s);
 hipError_t launch_join(const JoinArgs &a, hipStream_t s);
 hipError_t launch_rowmajor(const double *src, int64_t ld_src, int64_t rows, int32_t ncols, double *dst, hipStream_t s);

@@ -455,8 +455,9 @@ constexpr bool stage_fits() {
 // Staging (FUSE, where it fits): the asynchronous copies of the next chunk
 // are issued after the current chunk has been read from the staging area and
 // before its tails and QR are computed; they land while the QR runs.
+// bx0: the first workgroup of this task in the launch (batched launches).
 template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT, bool JOIN>
-__global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
+__device__ __forceinline__ void helmert_body(const HelmertArgs &a, int bx0) {
     // the compact QR's column loop reads R through loop-carried LDS addresses
     // the compiler cannot tell apart from the staging area, so it would wait
     // for the copies at its first column: no staging there
@@ -469,7 +470,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     __shared__ double wy_lds[WY ? kWavesPerBlock * kWyScratch : 1];
     const int lane = threadIdx.x & 63;
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int wave = blockIdx.x * kWavesPerBlock + wib;
+    const int wave = ((int)blockIdx.x - bx0) * kWavesPerBlock + wib;
     const bool active = wave < a.waves;
     if (!FUSE && !active) return;
     const int64_t c_begin = active ? a.nchunks * wave / a.waves : 0;
@@ -599,8 +600,23 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     }
     if constexpr (FUSE) {
         if (wib > 0) __syncthreads();
-        else store_r<NB>(a, rw, lane, blockIdx.x);
+        else store_r<NB>(a, rw, lane, (int)blockIdx.x - bx0);
     }
+}
+
+template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT, bool JOIN>
+__global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArgs a) {
+    helmert_body<NB, RPL, MODE, FUSE, OCC, ROT, JOIN>(a, 0);
+}
+
+// Upper (weighted, unfused) head/tail levels of independent tasks in one
+// launch: task t owns workgroups [wg0[t], wg0[t + 1]).  These levels are
+// small and bound by latency, so tasks side by side share it.
+template <int NB, int RPL, int OCC, bool ROT>
+__global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert_multi(HelmertBatch b) {
+    int t = 0;
+    while (t + 1 < b.count && (int)blockIdx.x >= b.wg0[t + 1]) ++t;
+    helmert_body<NB, RPL, 1, false, OCC, ROT, false>(b.a[t], b.wg0[t]);
 }
 
 // Dense TSQR step: workgroup b folds rows [b*4*tpw*T, (b+1)*4*tpw*T) (T rows
@@ -994,6 +1010,40 @@ hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int varian
         case 40:
             if (a.ncols > kFusedMaxCols) return hipErrorInvalidValue;   // wide tasks run in column chunks
             return variant == 1 ? helmert_nb<40, 1>(a, unit, fuse, s) : helmert_nb<40, 0>(a, unit, fuse, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int helmert_shape_class(int ncols) { return nb_for(ncols); }
+
+template <int NB, int V>
+hipError_t helmert_batch_nb(const HelmertBatch &b, hipStream_t s) {
+    constexpr int RPL = Shape<NB, V>::RPL, OCC = Shape<NB, V>::OCC;
+    constexpr bool ROT = Shape<NB, V>::ROT;
+    hipLaunchKernelGGL((k_helmert_multi<NB, RPL, OCC, ROT>), dim3(b.wg0[b.count]), dim3(64 * kWavesPerBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+template <int NB>
+hipError_t helmert_batch_v(const HelmertBatch &b, int variant, hipStream_t s) {
+    switch (variant) {
+        case 1: return helmert_batch_nb<NB, 1>(b, s);
+        case 2: return helmert_batch_nb<NB, 2>(b, s);
+        default: return helmert_batch_nb<NB, 0>(b, s);
+    }
+}
+
+hipError_t launch_helmert_batch(const HelmertBatch &b, int variant, hipStream_t s) {
+    if (b.count <= 0 || b.count > kHelmertBatch || b.wg0[b.count] <= 0) return hipErrorInvalidValue;
+    const int nb = nb_for(b.a[0].ncols);
+    for (int t = 0; t < b.count; ++t)
+        if (b.a[t].ncols > kFusedMaxCols || nb_for(b.a[t].ncols) != nb || b.a[t].wide_cols != 0 || b.a[t].join)
+            return hipErrorInvalidValue;
+    switch (nb) {
+        case 8: return helmert_batch_v<8>(b, variant, s);
+        case 16: return helmert_batch_v<16>(b, variant, s);
+        case 32: return helmert_batch_v<32>(b, variant, s);
+        case 40: return variant == 1 ? helmert_batch_nb<40, 1>(b, s) : helmert_batch_nb<40, 0>(b, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -90,6 +90,81 @@ JoinSrc join_src(const figaro_plan_s *p, const RelPlan &Rl, int v, const Buffers
     return js;
 }
 
+// Arguments of level li of head/tail task T reading its items from cur
+// (ld); fold: the level folds its tails into workgroup R's (the first level
+// of a fused narrow task).  With js, the first level reads its items
+// through the join view.
+HelmertArgs level_args(figaro_plan_s *p, Task &T, size_t li, const double *cur, int64_t ld, bool fuse, double *r0,
+                       int64_t ld_r0, int32_t *block_of_row, const JoinSrc *js, bool &fold) {
+    const Level &L = T.levels[li];
+    // the tails of a wide plan's wide heads_and_tails task go to its region,
+    // in the task's own columns
+    const bool region = fuse && T.d_region != nullptr;
+    const bool wide = T.ncols > kFusedMaxCols;
+    HelmertArgs a{};
+    a.in = cur;
+    a.ld_in = ld;
+    if (js && li == 0) {
+        a.join = 1;
+        a.js = *js;
+    }
+    a.ncols = T.ncols;
+    a.items = L.items;
+    a.pid = L.d_pid;
+    a.piece_start = L.d_piece_start;
+    a.phi_piece = L.d_phi_piece;
+    a.alpha = L.d_alpha;
+    a.beta = L.d_beta;
+    a.chunk_start = L.d_chunk_start;
+    a.chunk_piece0 = L.d_chunk_piece0;
+    a.nchunks = L.nchunks;
+    a.pieces_out = L.d_pieces;
+    a.ld_pieces = L.npieces;
+    a.stack = p->d_stack[0];
+    a.ld_stack = p->stack_ld[0];
+    a.stack_row0 = L.stack_row0;
+    a.n_total = p->n;
+    set_other_cols(a.other_cols, p->n, T.cols);
+    if (!wide)
+        for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint16_t)T.cols[c];
+    // upper levels of the fused pass write their tail rows into the
+    // stack, and so do all levels of a wide task
+    fold = fuse && li == 0 && !wide;
+    const bool to_stack = fuse && !fold;
+    a.r0 = to_stack ? (region ? T.d_region : p->d_stack[0]) : r0;
+    a.ld_r0 = to_stack ? (region ? T.region_ld : p->stack_ld[0]) : ld_r0;
+    a.r0_row0 = to_stack ? L.stack_row0 : L.r0_row0;
+    if (fold && !r0) a.r0 = nullptr;
+    a.block_of_row = to_stack ? nullptr : block_of_row;
+    a.block_id = T.block_id;
+    a.waves = L.waves;
+    if (wide) {
+        // column chunks, all in one launch: the tails of every column
+        // depend on that column only; the first chunk also writes the
+        // zeros of the columns outside the task
+        a.in = a.join ? nullptr : cur;
+        a.join_col0 = 0;
+        a.ncols = kChunkCols;
+        a.wide_cols = T.ncols;
+        a.cols_ident = region ? 1 : 0;
+        a.wide_colmap = T.d_cols16;
+    }
+    return a;
+}
+
+// One level of a head/tail task on its own.
+figaro_status launch_level(figaro_plan_s *p, Task &T, size_t li, const HelmertArgs &a, bool fold, hipStream_t s) {
+    const Level &L = T.levels[li];
+    if (T.ncols > kFusedMaxCols && !T.d_cols16)
+        return set_error(p, FIGARO_EINVAL, "wide task without a device column table");
+    const int kind = li > 0 ? 2 : (L.unit ? 0 : 1);
+    const double bytes = 8.0 * (double)L.items * T.ncols;
+    const double flops = fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
+    ProfScope ps(p, s, kind, bytes, flops);
+    FIGARO_TRY(launch_helmert(a, L.unit, fold, L.variant, s));
+    return FIGARO_OK;
+}
+
 // Run the levels of one head/tail task; returns the group sums.  With js,
 // the first level reads its items through the join view (in is unused).
 figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_in, bool fuse, double *r0,
@@ -97,74 +172,80 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
                        int64_t *ld_groups, const JoinSrc *js = nullptr) {
     const double *cur = in;
     int64_t ld = ld_in;
-    // the tails of a wide plan's wide heads_and_tails task go to its region,
-    // in the task's own columns
-    const bool region = fuse && T.d_region != nullptr;
-    const bool wide = T.ncols > kFusedMaxCols;
-    for (auto &L : T.levels) {
-        HelmertArgs a{};
-        a.in = cur;
-        a.ld_in = ld;
-        if (js && &L == &T.levels[0]) {
-            a.join = 1;
-            a.js = *js;
-        }
-        a.ncols = T.ncols;
-        a.items = L.items;
-        a.pid = L.d_pid;
-        a.piece_start = L.d_piece_start;
-        a.phi_piece = L.d_phi_piece;
-        a.alpha = L.d_alpha;
-        a.beta = L.d_beta;
-        a.chunk_start = L.d_chunk_start;
-        a.chunk_piece0 = L.d_chunk_piece0;
-        a.nchunks = L.nchunks;
-        a.pieces_out = L.d_pieces;
-        a.ld_pieces = L.npieces;
-        a.stack = p->d_stack[0];
-        a.ld_stack = p->stack_ld[0];
-        a.stack_row0 = L.stack_row0;
-        a.n_total = p->n;
-        set_other_cols(a.other_cols, p->n, T.cols);
-        if (!wide)
-            for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint16_t)T.cols[c];
-        // upper levels of the fused pass write their tail rows into the
-        // stack, and so do all levels of a wide task
-        const bool fold = fuse && (&L == &T.levels[0]) && !wide;
-        const bool to_stack = fuse && !fold;
-        a.r0 = to_stack ? (region ? T.d_region : p->d_stack[0]) : r0;
-        a.ld_r0 = to_stack ? (region ? T.region_ld : p->stack_ld[0]) : ld_r0;
-        a.r0_row0 = to_stack ? L.stack_row0 : L.r0_row0;
-        if (fold && !r0) a.r0 = nullptr;
-        a.block_of_row = to_stack ? nullptr : block_of_row;
-        a.block_id = T.block_id;
-        a.waves = L.waves;
-        {
-            const int kind = (&L != &T.levels[0]) ? 2 : (L.unit ? 0 : 1);
-            const double bytes = 8.0 * (double)L.items * T.ncols;
-            const double flops = fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
-            ProfScope ps(p, s, kind, bytes, flops);
-            if (!wide) {
-                FIGARO_TRY(launch_helmert(a, L.unit, fold, L.variant, s));
-            } else {
-                // column chunks, all in one launch: the tails of every
-                // column depend on that column only; the first chunk also
-                // writes the zeros of the columns outside the task
-                if (!T.d_cols16) return set_error(p, FIGARO_EINVAL, "wide task without a device column table");
-                a.in = a.join ? nullptr : cur;
-                a.join_col0 = 0;
-                a.ncols = kChunkCols;
-                a.wide_cols = T.ncols;
-                a.cols_ident = region ? 1 : 0;
-                a.wide_colmap = T.d_cols16;
-                FIGARO_TRY(launch_helmert(a, L.unit, false, L.variant, s));
-            }
-        }
-        cur = L.d_pieces;
-        ld = L.npieces;
+    for (size_t li = 0; li < T.levels.size(); ++li) {
+        bool fold = false;
+        const HelmertArgs a = level_args(p, T, li, cur, ld, fuse, r0, ld_r0, block_of_row, js, fold);
+        if (figaro_status st = launch_level(p, T, li, a, fold, s); st != FIGARO_OK) return st;
+        cur = T.levels[li].d_pieces;
+        ld = T.levels[li].npieces;
     }
     *group_sums = cur;
     *ld_groups = ld;
+    return FIGARO_OK;
+}
+
+// heads_and_tails of every relation (they read the relation's own values
+// only, so they are independent of each other and of the joins): level by
+// level over all tasks, the upper levels of tasks of one tile shape
+// sharing launches (they are small and bound by latency).  Leaves each
+// relation's key-group sums in B.own.
+figaro_status run_heads_and_tails(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse,
+                                  double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, Buffers &B) {
+    std::vector<int> tasks;
+    size_t levels = 0;
+    for (int v : p->post) {
+        B.own[v] = values[v];
+        B.ld_own[v] = ld[v];
+        if (p->rel[v].a2.active) {
+            tasks.push_back(v);
+            levels = std::max(levels, p->rel[v].a2.levels.size());
+        }
+    }
+    for (size_t li = 0; li < levels; ++li) {
+        // pending batch per (tile shape, variant)
+        std::vector<std::pair<std::pair<int, int>, HelmertBatch>> open;
+        std::vector<double> open_bytes;
+        auto flush = [&](size_t k) -> figaro_status {
+            HelmertBatch &b = open[k].second;
+            if (b.count == 0) return FIGARO_OK;
+            ProfScope ps(p, s, 2, open_bytes[k], 0.0);
+            FIGARO_TRY(launch_helmert_batch(b, open[k].first.second, s));
+            b.count = 0;
+            b.wg0[0] = 0;
+            open_bytes[k] = 0.0;
+            return FIGARO_OK;
+        };
+        for (int v : tasks) {
+            Task &T = p->rel[v].a2;
+            if (li >= T.levels.size()) continue;
+            const Level &L = T.levels[li];
+            bool fold = false;
+            const HelmertArgs a =
+                level_args(p, T, li, B.own[v], B.ld_own[v], fuse, r0, ld_r0, block_of_row, nullptr, fold);
+            if (li == 0 || fold || L.unit || T.ncols > kFusedMaxCols || L.waves <= 0 || L.nchunks <= 0) {
+                if (figaro_status st = launch_level(p, T, li, a, fold, s); st != FIGARO_OK) return st;
+            } else {
+                const std::pair<int, int> key{helmert_shape_class(T.ncols), L.variant};
+                size_t k = 0;
+                while (k < open.size() && open[k].first != key) ++k;
+                if (k == open.size()) {
+                    open.push_back({key, HelmertBatch{}});
+                    open_bytes.push_back(0.0);
+                }
+                HelmertBatch &b = open[k].second;
+                b.a[b.count] = a;
+                b.wg0[b.count + 1] = b.wg0[b.count] + (L.waves + waves_per_block() - 1) / waves_per_block();
+                ++b.count;
+                open_bytes[k] += 8.0 * (double)L.items * T.ncols;
+                if (b.count == kHelmertBatch)
+                    if (figaro_status st = flush(k); st != FIGARO_OK) return st;
+            }
+            B.own[v] = L.d_pieces;
+            B.ld_own[v] = L.npieces;
+        }
+        for (size_t k = 0; k < open.size(); ++k)
+            if (figaro_status st = flush(k); st != FIGARO_OK) return st;
+    }
     return FIGARO_OK;
 }
 
@@ -224,17 +305,11 @@ figaro_status forward(figaro_plan_s *p, const double *const *values, const int64
     B.ld_own.assign(p->r, 0);
     B.sigma.assign(p->r, nullptr);
     B.ld_sigma.assign(p->r, 0);
+    // heads_and_tails: own key-group sums and the tails of every S_v
+    if (figaro_status st = run_heads_and_tails(p, values, ld, fuse, r0, ld_r0, block_of_row, s, B); st != FIGARO_OK)
+        return st;
     for (int v : p->post) {
         RelPlan &Rl = p->rel[v];
-        // heads_and_tails: own key-group sums and the tails of S_v
-        if (Rl.a2.active) {
-            figaro_status st = run_task(p, Rl.a2, values[v], ld[v], fuse, r0, ld_r0, block_of_row, s, &B.own[v],
-                                        &B.ld_own[v]);
-            if (st != FIGARO_OK) return st;
-        } else {
-            B.own[v] = values[v];
-            B.ld_own[v] = ld[v];
-        }
         const double *items = B.own[v];
         int64_t ld_items = B.ld_own[v];
         const bool in_place = Rl.fuse_join && join_in_place;
