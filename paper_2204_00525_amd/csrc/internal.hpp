@@ -254,9 +254,9 @@ struct WideQr;
 // Launchers (kernels.hip)
 // ---------------------------------------------------------------------------
 hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int variant, hipStream_t s);
-// Weighted unfused levels of up to kHelmertBatch tasks of one tile shape
-// (columns <= kFusedMaxCols, same nb_for(ncols) and variant).
-hipError_t launch_helmert_batch(const HelmertBatch &b, int variant, hipStream_t s);
+// One level of up to kHelmertBatch tasks of one tile shape (columns <=
+// kFusedMaxCols, same nb_for(ncols), variant, unit counts and folding).
+hipError_t launch_helmert_batch(const HelmertBatch &b, bool unit, bool fuse, int variant, hipStream_t s);
 int helmert_shape_class(int ncols);
 hipError_t launch_dense(const DenseArgs &a, int variant, hipStream_t s);
 hipError_t launch_join(const JoinArgs &a, hipStream_t s);

@@ -609,14 +609,15 @@ __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert(HelmertArg
     helmert_body<NB, RPL, MODE, FUSE, OCC, ROT, JOIN>(a, 0);
 }
 
-// Upper (weighted, unfused) head/tail levels of independent tasks in one
-// launch: task t owns workgroups [wg0[t], wg0[t + 1]).  These levels are
-// small and bound by latency, so tasks side by side share it.
-template <int NB, int RPL, int OCC, bool ROT>
+// The same level of independent tasks in one launch: task t owns
+// workgroups [wg0[t], wg0[t + 1]).  Upper levels are small and bound by
+// latency, so tasks side by side share it; first levels that each fill the
+// chip overlap one task's last tiles with the next one's first.
+template <int NB, int RPL, int MODE, bool FUSE, int OCC, bool ROT>
 __global__ __launch_bounds__(64 * kWavesPerBlock, OCC) void k_helmert_multi(HelmertBatch b) {
     int t = 0;
     while (t + 1 < b.count && (int)blockIdx.x >= b.wg0[t + 1]) ++t;
-    helmert_body<NB, RPL, 1, false, OCC, ROT, false>(b.a[t], b.wg0[t]);
+    helmert_body<NB, RPL, MODE, FUSE, OCC, ROT, false>(b.a[t], b.wg0[t]);
 }
 
 // Dense TSQR step: workgroup b folds rows [b*4*tpw*T, (b+1)*4*tpw*T) (T rows
@@ -1017,33 +1018,41 @@ hipError_t launch_helmert(const HelmertArgs &a, bool unit, bool fuse, int varian
 int helmert_shape_class(int ncols) { return nb_for(ncols); }
 
 template <int NB, int V>
-hipError_t helmert_batch_nb(const HelmertBatch &b, hipStream_t s) {
+hipError_t helmert_batch_nb(const HelmertBatch &b, bool unit, bool fuse, hipStream_t s) {
     constexpr int RPL = Shape<NB, V>::RPL, OCC = Shape<NB, V>::OCC;
     constexpr bool ROT = Shape<NB, V>::ROT;
-    hipLaunchKernelGGL((k_helmert_multi<NB, RPL, OCC, ROT>), dim3(b.wg0[b.count]), dim3(64 * kWavesPerBlock), 0, s, b);
+    const dim3 grid(b.wg0[b.count]), block(64 * kWavesPerBlock);
+    if (unit) {
+        if (fuse) hipLaunchKernelGGL((k_helmert_multi<NB, RPL, 0, true, OCC, ROT>), grid, block, 0, s, b);
+        else hipLaunchKernelGGL((k_helmert_multi<NB, RPL, 0, false, OCC, ROT>), grid, block, 0, s, b);
+    } else {
+        if (fuse) hipLaunchKernelGGL((k_helmert_multi<NB, RPL, 1, true, OCC, ROT>), grid, block, 0, s, b);
+        else hipLaunchKernelGGL((k_helmert_multi<NB, RPL, 1, false, OCC, ROT>), grid, block, 0, s, b);
+    }
     return hipGetLastError();
 }
 
 template <int NB>
-hipError_t helmert_batch_v(const HelmertBatch &b, int variant, hipStream_t s) {
+hipError_t helmert_batch_v(const HelmertBatch &b, bool unit, bool fuse, int variant, hipStream_t s) {
     switch (variant) {
-        case 1: return helmert_batch_nb<NB, 1>(b, s);
-        case 2: return helmert_batch_nb<NB, 2>(b, s);
-        default: return helmert_batch_nb<NB, 0>(b, s);
+        case 1: return helmert_batch_nb<NB, 1>(b, unit, fuse, s);
+        case 2: return helmert_batch_nb<NB, 2>(b, unit, fuse, s);
+        default: return helmert_batch_nb<NB, 0>(b, unit, fuse, s);
     }
 }
 
-hipError_t launch_helmert_batch(const HelmertBatch &b, int variant, hipStream_t s) {
+hipError_t launch_helmert_batch(const HelmertBatch &b, bool unit, bool fuse, int variant, hipStream_t s) {
     if (b.count <= 0 || b.count > kHelmertBatch || b.wg0[b.count] <= 0) return hipErrorInvalidValue;
     const int nb = nb_for(b.a[0].ncols);
     for (int t = 0; t < b.count; ++t)
         if (b.a[t].ncols > kFusedMaxCols || nb_for(b.a[t].ncols) != nb || b.a[t].wide_cols != 0 || b.a[t].join)
             return hipErrorInvalidValue;
     switch (nb) {
-        case 8: return helmert_batch_v<8>(b, variant, s);
-        case 16: return helmert_batch_v<16>(b, variant, s);
-        case 32: return helmert_batch_v<32>(b, variant, s);
-        case 40: return variant == 1 ? helmert_batch_nb<40, 1>(b, s) : helmert_batch_nb<40, 0>(b, s);
+        case 8: return helmert_batch_v<8>(b, unit, fuse, variant, s);
+        case 16: return helmert_batch_v<16>(b, unit, fuse, variant, s);
+        case 32: return helmert_batch_v<32>(b, unit, fuse, variant, s);
+        case 40:
+            return variant == 1 ? helmert_batch_nb<40, 1>(b, unit, fuse, s) : helmert_batch_nb<40, 0>(b, unit, fuse, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -186,9 +186,10 @@ figaro_status run_task(figaro_plan_s *p, Task &T, const double *in, int64_t ld_i
 
 // heads_and_tails of every relation (they read the relation's own values
 // only, so they are independent of each other and of the joins): level by
-// level over all tasks, the upper levels of tasks of one tile shape
-// sharing launches (they are small and bound by latency).  Leaves each
-// relation's key-group sums in B.own.
+// level over all tasks, the same level of tasks of one tile shape sharing
+// launches (upper levels are small and bound by latency; first levels that
+// each fill the chip overlap one task's last tiles with the next one's
+// first).  Leaves each relation's key-group sums in B.own.
 figaro_status run_heads_and_tails(figaro_plan_s *p, const double *const *values, const int64_t *ld, bool fuse,
                                   double *r0, int64_t ld_r0, int32_t *block_of_row, hipStream_t s, Buffers &B) {
     std::vector<int> tasks;
@@ -201,18 +202,21 @@ figaro_status run_heads_and_tails(figaro_plan_s *p, const double *const *values,
             levels = std::max(levels, p->rel[v].a2.levels.size());
         }
     }
+    struct Open {
+        int shape, variant;
+        bool unit, fold;
+        HelmertBatch b;
+        double bytes, flops;
+    };
     for (size_t li = 0; li < levels; ++li) {
-        // pending batch per (tile shape, variant)
-        std::vector<std::pair<std::pair<int, int>, HelmertBatch>> open;
-        std::vector<double> open_bytes;
-        auto flush = [&](size_t k) -> figaro_status {
-            HelmertBatch &b = open[k].second;
-            if (b.count == 0) return FIGARO_OK;
-            ProfScope ps(p, s, 2, open_bytes[k], 0.0);
-            FIGARO_TRY(launch_helmert_batch(b, open[k].first.second, s));
-            b.count = 0;
-            b.wg0[0] = 0;
-            open_bytes[k] = 0.0;
+        std::vector<Open> open;
+        auto flush = [&](Open &o) -> figaro_status {
+            if (o.b.count == 0) return FIGARO_OK;
+            ProfScope ps(p, s, li > 0 ? 2 : (o.unit ? 0 : 1), o.bytes, o.flops);
+            FIGARO_TRY(launch_helmert_batch(o.b, o.unit, o.fold, o.variant, s));
+            o.b.count = 0;
+            o.b.wg0[0] = 0;
+            o.bytes = o.flops = 0.0;
             return FIGARO_OK;
         };
         for (int v : tasks) {
@@ -222,29 +226,29 @@ figaro_status run_heads_and_tails(figaro_plan_s *p, const double *const *values,
             bool fold = false;
             const HelmertArgs a =
                 level_args(p, T, li, B.own[v], B.ld_own[v], fuse, r0, ld_r0, block_of_row, nullptr, fold);
-            if (li == 0 || fold || L.unit || T.ncols > kFusedMaxCols || L.waves <= 0 || L.nchunks <= 0) {
+            if (T.ncols > kFusedMaxCols || L.waves <= 0 || L.nchunks <= 0) {
                 if (figaro_status st = launch_level(p, T, li, a, fold, s); st != FIGARO_OK) return st;
             } else {
-                const std::pair<int, int> key{helmert_shape_class(T.ncols), L.variant};
+                const int shape = helmert_shape_class(T.ncols);
                 size_t k = 0;
-                while (k < open.size() && open[k].first != key) ++k;
-                if (k == open.size()) {
-                    open.push_back({key, HelmertBatch{}});
-                    open_bytes.push_back(0.0);
-                }
-                HelmertBatch &b = open[k].second;
-                b.a[b.count] = a;
-                b.wg0[b.count + 1] = b.wg0[b.count] + (L.waves + waves_per_block() - 1) / waves_per_block();
-                ++b.count;
-                open_bytes[k] += 8.0 * (double)L.items * T.ncols;
-                if (b.count == kHelmertBatch)
-                    if (figaro_status st = flush(k); st != FIGARO_OK) return st;
+                while (k < open.size() && !(open[k].shape == shape && open[k].variant == L.variant &&
+                                            open[k].unit == L.unit && open[k].fold == fold))
+                    ++k;
+                if (k == open.size()) open.push_back(Open{shape, L.variant, L.unit, fold, HelmertBatch{}, 0.0, 0.0});
+                Open &o = open[k];
+                o.b.a[o.b.count] = a;
+                o.b.wg0[o.b.count + 1] = o.b.wg0[o.b.count] + (L.waves + waves_per_block() - 1) / waves_per_block();
+                ++o.b.count;
+                o.bytes += 8.0 * (double)L.items * T.ncols;
+                o.flops += fold ? 2.0 * (double)L.items * T.ncols * T.ncols : 0.0;
+                if (o.b.count == kHelmertBatch)
+                    if (figaro_status st = flush(o); st != FIGARO_OK) return st;
             }
             B.own[v] = L.d_pieces;
             B.ld_own[v] = L.npieces;
         }
-        for (size_t k = 0; k < open.size(); ++k)
-            if (figaro_status st = flush(k); st != FIGARO_OK) return st;
+        for (Open &o : open)
+            if (figaro_status st = flush(o); st != FIGARO_OK) return st;
     }
     return FIGARO_OK;
 }
