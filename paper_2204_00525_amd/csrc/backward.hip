@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "bwd_batch.hpp"
 #include "device_common.hpp"
 #include "tails.hpp"
 
@@ -258,8 +259,9 @@ __device__ __forceinline__ void tile_times_k(const double (&x)[RPL][NB], const d
 // (tile_tails) and dT = T K_blk goes through bwd_finish.
 // ROWS: the output is row-major with exactly NB columns (the gradient of
 // joined heads), written through a row-major tile in LDS.
+// bx0: the first workgroup of this task in the launch (batched launches).
 template <int NB, int RPL, int MODE, bool ROWS>
-__global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
+__device__ __forceinline__ void helmert_bwd_body(const HelmertBwdArgs &a, int bx0) {
     __shared__ double sK[NB * NB];   // sK[e * NB + c] = K[colmap[e]][colmap[c]], zero outside ncols
     __shared__ double stage[kWavesPerBlock * 64 * RPL];   // per-wave store staging
     __shared__ double rstage[ROWS ? kWavesPerBlock * 64 * (RPL * NB + 1) : 1];   // per-wave row-major tile
@@ -269,7 +271,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wave = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+    const int wave = ((int)blockIdx.x - bx0) * kWavesPerBlock + (threadIdx.x >> 6);
     if (wave >= a.waves) return;
     const int64_t c_begin = a.nchunks * wave / a.waves;
     const int64_t c_end = a.nchunks * (wave + 1) / a.waves;
@@ -292,6 +294,20 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdA
         bwd_finish<NB, RPL>(a, g, ti, cs, ce, lane, 0, a.ncols, st,
                             ROWS ? rstage + (threadIdx.x >> 6) * (64 * (RPL * NB + 1)) : nullptr);
     }
+}
+
+template <int NB, int RPL, int MODE, bool ROWS>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd(HelmertBwdArgs a) {
+    helmert_bwd_body<NB, RPL, MODE, ROWS>(a, 0);
+}
+
+// The same level of independent tasks in one launch: task t owns
+// workgroups [wg0[t], wg0[t + 1]).
+template <int NB, int RPL, int MODE>
+__global__ __launch_bounds__(64 * kWavesPerBlock) void k_helmert_bwd_multi(HelmertBwdBatch b) {
+    int t = 0;
+    while (t + 1 < b.count && (int)blockIdx.x >= b.wg0[t + 1]) ++t;
+    helmert_bwd_body<NB, RPL, MODE, false>(b.a[t], b.wg0[t]);
 }
 
 // The same for wide levels (ncols > kChunkCols), in column chunks of
@@ -473,6 +489,29 @@ hipError_t launch_helmert_bwd(const HelmertBwdArgs &a, bool unit, hipStream_t s)
         case 16: return helmert_bwd_nb<16>(a, unit, s);
         default: return helmert_bwd_nb<32>(a, unit, s);
     }
+}
+
+int helmert_bwd_shape_class(int ncols) { return ncols > kChunkCols ? 0 : nb_bwd(ncols); }
+
+template <int NB>
+void helmert_bwd_batch_nb(const HelmertBwdBatch &b, bool unit, hipStream_t s) {
+    constexpr int RPL = (NB == 8) ? 8 : (NB == 16 ? 4 : 2);
+    const dim3 grid(b.wg0[b.count]), block(64 * kWavesPerBlock);
+    if (unit) hipLaunchKernelGGL((k_helmert_bwd_multi<NB, RPL, 0>), grid, block, 0, s, b);
+    else hipLaunchKernelGGL((k_helmert_bwd_multi<NB, RPL, 1>), grid, block, 0, s, b);
+}
+
+hipError_t launch_helmert_bwd_batch(const HelmertBwdBatch &b, bool unit, hipStream_t s) {
+    if (b.count <= 0 || b.count > kHelmertBwdBatch || b.wg0[b.count] <= 0) return hipErrorInvalidValue;
+    const int nb = helmert_bwd_shape_class(b.a[0].ncols);
+    for (int t = 0; t < b.count; ++t)
+        if (nb == 0 || helmert_bwd_shape_class(b.a[t].ncols) != nb || b.a[t].gout_rowmajor) return hipErrorInvalidValue;
+    switch (nb) {
+        case 8: helmert_bwd_batch_nb<8>(b, unit, s); break;
+        case 16: helmert_bwd_batch_nb<16>(b, unit, s); break;
+        default: helmert_bwd_batch_nb<32>(b, unit, s);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_join_bwd(const JoinBwdArgs &a_in, hipStream_t s) {

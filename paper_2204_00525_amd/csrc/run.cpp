@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "internal.hpp"
+#include "bwd_batch.hpp"
 #include "../../include/figaro_debug.h"
 
 namespace figaro {
@@ -469,6 +470,93 @@ figaro_status run_task_bwd(figaro_plan_s *p, Task &T, const double *in, int64_t 
     return FIGARO_OK;
 }
 
+// Arguments of the backward of level l of task T (items of level 0: in).
+HelmertBwdArgs level_bwd_args(figaro_plan_s *p, Task &T, int l, const double *in, int64_t ld_in, Target out) {
+    Level &L = T.levels[l];
+    HelmertBwdArgs a{};
+    a.in = (l == 0) ? in : T.levels[l - 1].d_pieces;
+    a.ld_in = (l == 0) ? ld_in : T.levels[l - 1].npieces;
+    a.ncols = T.ncols;
+    a.pid = L.d_pid;
+    a.piece_start = L.d_piece_start;
+    a.phi_piece = L.d_phi_piece;
+    a.alpha = L.d_alpha;
+    a.beta = L.d_beta;
+    a.chunk_start = L.d_chunk_start;
+    a.nchunks = L.nchunks;
+    a.K = p->d_K;
+    a.n_total = p->n;
+    for (int c = 0; c < T.ncols; ++c) a.colmap[c] = (uint8_t)T.cols[c];
+    a.gpieces = L.d_gpieces;
+    a.ld_gp = L.npieces;
+    a.gout = (l == 0) ? out.p : T.levels[l - 1].d_gpieces;
+    a.ld_gout = (l == 0) ? out.ld : T.levels[l - 1].npieces;
+    a.gout_rowmajor = (l == 0 && out.rowmajor) ? 1 : 0;
+    a.waves = (int32_t)std::min<int64_t>(L.nchunks, 8192);
+    return a;
+}
+
+// Backward of every relation's heads_and_tails task (step r: level
+// levels - 1 - r of each task that has it), the same step of tasks of one
+// shape class and count mode in shared launches.
+figaro_status run_heads_and_tails_bwd(figaro_plan_s *p, const double *const *values, const int64_t *ld,
+                                      double *const *dvalues, const int64_t *ld_dv, hipStream_t s) {
+    std::vector<int> tasks;
+    size_t steps = 0;
+    for (int v : p->post)
+        if (p->rel[v].a2.active) {
+            tasks.push_back(v);
+            steps = std::max(steps, p->rel[v].a2.levels.size());
+        }
+    struct Open {
+        int shape;
+        bool unit;
+        HelmertBwdBatch b;
+        double bytes, flops;
+    };
+    for (size_t r = 0; r < steps; ++r) {
+        std::vector<Open> open;
+        auto flush = [&](Open &o) -> figaro_status {
+            if (o.b.count == 0) return FIGARO_OK;
+            ProfScope ps(p, s, 6, o.bytes, o.flops);
+            FIGARO_TRY(launch_helmert_bwd_batch(o.b, o.unit, s));
+            o.b.count = 0;
+            o.b.wg0[0] = 0;
+            o.bytes = o.flops = 0.0;
+            return FIGARO_OK;
+        };
+        for (int v : tasks) {
+            Task &T = p->rel[v].a2;
+            if (r >= T.levels.size()) continue;
+            const int l = (int)(T.levels.size() - 1 - r);
+            Level &L = T.levels[l];
+            const HelmertBwdArgs a = level_bwd_args(p, T, l, values[v], ld[v], Target{dvalues[v], ld_dv[v]});
+            const double bytes = 8.0 * (double)L.items * T.ncols * 2.0;
+            const double flops = 2.0 * (double)L.items * T.ncols * T.ncols;
+            const int shape = helmert_bwd_shape_class(T.ncols);
+            if (shape == 0 || a.waves <= 0 || a.nchunks <= 0) {
+                ProfScope ps(p, s, 6, bytes, flops);
+                FIGARO_TRY(launch_helmert_bwd(a, L.unit, s));
+                continue;
+            }
+            size_t k = 0;
+            while (k < open.size() && !(open[k].shape == shape && open[k].unit == L.unit)) ++k;
+            if (k == open.size()) open.push_back(Open{shape, L.unit, HelmertBwdBatch{}, 0.0, 0.0});
+            Open &o = open[k];
+            o.b.a[o.b.count] = a;
+            o.b.wg0[o.b.count + 1] = o.b.wg0[o.b.count] + (a.waves + waves_per_block() - 1) / waves_per_block();
+            ++o.b.count;
+            o.bytes += bytes;
+            o.flops += flops;
+            if (o.b.count == kHelmertBwdBatch)
+                if (figaro_status st = flush(o); st != FIGARO_OK) return st;
+        }
+        for (Open &o : open)
+            if (figaro_status st = flush(o); st != FIGARO_OK) return st;
+    }
+    return FIGARO_OK;
+}
+
 figaro_status backward(figaro_plan_s *p, const double *const *values, const int64_t *ld, const double *R,
                        const double *dR, double *const *dvalues, const int64_t *ld_dv, hipStream_t s) {
     // recompute the forward intermediates (piece sums, joined heads)
@@ -536,12 +624,11 @@ figaro_status backward(figaro_plan_s *p, const double *const *values, const int6
             ProfScope ps(p, s, 6, 16.0 * (double)Rl.G * Rl.nsub, 0.0);
             FIGARO_TRY(launch_join_bwd(j, s));
         }
-        if (Rl.a2.active) {
-            st = run_task_bwd(p, Rl.a2, values[v], ld[v], Target{dvalues[v], ld_dv[v]}, s);
-            if (st != FIGARO_OK) return st;
-        }
     }
-    return FIGARO_OK;
+    // heads_and_tails of every relation last: each needs only the gradient
+    // of its key-group sums, complete now; their levels from the top down,
+    // the same step of tasks of one tile shape sharing launches
+    return run_heads_and_tails_bwd(p, values, ld, dvalues, ld_dv, s);
 }
 
 }  // namespace
